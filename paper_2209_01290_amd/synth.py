@@ -1,0 +1,91 @@
+"""Seeded synthetic inputs: uniform coefficients in [0, q).
+
+This module holds no arithmetic of the method. It only draws random words, so
+both the GPU path and the CPU oracle can be fed the very same operands.
+
+Generator: SplitMix64's output function (Steele, Lea and Flood, "Fast
+splittable pseudorandom number generators", OOPSLA 2014) used in counter mode:
+
+    mix(z)    = z ^= z >> 30; z *= 0xBF58476D1CE4E5B9;
+                z ^= z >> 27; z *= 0x94D049BB133111EB; z ^= z >> 31
+    key(seed, ids...) : k = mix(seed); for each id: k = mix(k + G*(id+1))
+    word(k, j) = mix(k + G*(j+1)),        G = 0x9E3779B97F4A7C15
+
+A coefficient takes the top len(q) bits of its word and is redrawn from the
+same counter under the key mix(k ^ attempt) while it is >= q, so every value is
+uniform on [0, q). All arithmetic is modulo 2^64.
+
+Stream ids name an operand: (request, limb, poly, operand) with operand 0 for a
+and 1 for b. Seeds are 220901290 + k for workload k (the paper's arXiv id).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+G = np.uint64(0x9E3779B97F4A7C15)
+C1 = np.uint64(0xBF58476D1CE4E5B9)
+C2 = np.uint64(0x94D049BB133111EB)
+SEED_BASE = 220901290
+
+_M64 = (1 << 64) - 1
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    z = z ^ (z >> np.uint64(30))
+    z = z * C1
+    z = z ^ (z >> np.uint64(27))
+    z = z * C2
+    return z ^ (z >> np.uint64(31))
+
+
+def _mix_int(z: int) -> int:
+    z &= _M64
+    z ^= z >> 30
+    z = (z * 0xBF58476D1CE4E5B9) & _M64
+    z ^= z >> 27
+    z = (z * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def key(seed: int, *ids: int) -> int:
+    k = _mix_int(seed)
+    for i in ids:
+        k = _mix_int(k + 0x9E3779B97F4A7C15 * (int(i) + 1))
+    return k
+
+
+def words(k: int, n: int) -> np.ndarray:
+    """n raw 64-bit words of stream k."""
+    j = np.arange(1, n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix(np.uint64(k) + G * j)
+
+
+def uniform_mod(k: int, n: int, q: int) -> np.ndarray:
+    """n coefficients uniform on [0, q) from stream k."""
+    bits = int(q).bit_length()
+    shift = np.uint64(64 - bits)
+    qq = np.uint64(q)
+    with np.errstate(over="ignore"):
+        v = words(k, n) >> shift
+        bad = np.nonzero(v >= qq)[0]
+        attempt = 1
+        while bad.size:
+            k2 = _mix_int(k ^ attempt)
+            j = bad.astype(np.uint64) + np.uint64(1)
+            v[bad] = _mix(np.uint64(k2) + G * j) >> shift
+            bad = bad[v[bad] >= qq]
+            attempt += 1
+    return v
+
+
+def operands(seed: int, q_per_limb, polys: int, N: int, request: int = 0):
+    """(a, b) as uint64 arrays of shape [limbs][polys][N]; limb l uses q_per_limb[l]."""
+    L = len(q_per_limb)
+    a = np.empty((L, polys, N), dtype=np.uint64)
+    b = np.empty((L, polys, N), dtype=np.uint64)
+    for l, q in enumerate(q_per_limb):
+        for p in range(polys):
+            a[l, p] = uniform_mod(key(seed, request, l, p, 0), N, int(q))
+            b[l, p] = uniform_mod(key(seed, request, l, p, 1), N, int(q))
+    return a, b
