@@ -1,0 +1,139 @@
+/*
+ * pm.h - exact negacyclic polynomial multiplication in Z_q[x]/(x^N + 1) on
+ * AMD MI355X (gfx950), C ABI.
+ *
+ * Method (Sec. III-A of the paper, Eq. 2): c = a (*) b is computed as
+ *     c = GS'_{psi^-1}( CT_psi(a) . CT_psi(b) )
+ * where CT_psi is the merged Cooley-Tukey NTT (Alg. 5: normal order in,
+ * bit-reversed order out, powers of psi folded into the twiddles), "." is the
+ * pointwise product mod q, and GS'_{psi^-1} is the merged Gentleman-Sande NTT
+ * (Alg. 6: bit-reversed in, normal out) whose butterflies halve both outputs,
+ * which merges the 1/N scaling. Every product is reduced with the paper's
+ * Barrett variant (Alg. 4, constant mu = floor(2^(2m+1)/q), m = len(q),
+ * at most one correctional subtraction). Arithmetic is exact: every output
+ * word is the canonical residue in [0, q).
+ *
+ * Conventions for every entry point:
+ *   - Array pointers marked "device" are caller-owned device memory (e.g.
+ *     torch tensors). The library never frees them. uint64 words, 8-byte
+ *     aligned. Pointers marked "host" are read on the host during the call.
+ *   - Batch layout is [limb][poly][N]: `limbs` moduli, each with
+ *     `polys_per_limb` polynomials of N contiguous coefficients. Limb l uses
+ *     modulus q[l] and twiddle tables psi_br + l*N, psi_inv_br + l*N.
+ *   - Coefficient domain is normal order. The NTT domain is bit-reversed
+ *     order: position p holds the value at psi^(2*br(p)+1), br over log2 N bits.
+ *   - Twiddle tables: psi_br[i] = psi^br(i) and psi_inv_br[i] = psi^-br(i) for
+ *     a primitive 2N-th root of unity psi (psi^N = q-1); entry 0 is never read.
+ *     pm_make_tables() builds them.
+ *   - Inputs must be canonical (< q); non-canonical input gives unspecified
+ *     (but memory-safe) output.
+ *   - Calls are stream-ordered and asynchronous: `stream` is a hipStream_t
+ *     (NULL = the default stream). Argument errors are reported before any
+ *     work is enqueued.
+ *   - Return value: PM_OK (0) or a negative PM_E* code; pm_last_error()
+ *     returns a message for the calling thread. No C++ exception crosses the ABI.
+ *   - Limits: N a power of two with 2 <= N <= 2^17; q odd with
+ *     3 <= q < 2^62 (Alg. 4 needs len(q) <= word size - 2) and 2N | q - 1
+ *     (the NTT setup of Sec. III-A).
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PM_OK 0
+#define PM_EINVAL (-1)        /* bad argument: size, modulus, pointer, alignment */
+#define PM_EUNSUPPORTED (-2)  /* valid request outside what this build implements */
+#define PM_ENOMEM (-3)        /* a device allocation made by the library failed */
+#define PM_EHIP (-4)          /* the HIP runtime reported an error */
+
+typedef void *pm_stream_t;    /* a hipStream_t */
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *pm_last_error(void);
+
+/*
+ * c[i] = a[i] * b[i] mod q for i < n, by Alg. 4 (Sec. II-B).
+ * a, b, c: device, n words each (c may alias a or b). q: 2 <= q < 2^62.
+ * Errors: PM_EINVAL for n == 0, a null or misaligned pointer, or q out of range.
+ */
+int pm_barrett_mulmod(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t n, uint64_t q,
+                      pm_stream_t stream);
+
+/*
+ * In-place forward merged CT NTT (Alg. 5) of limbs*polys_per_limb polynomials.
+ * x: device [limbs][polys_per_limb][N], normal order in, bit-reversed out.
+ * q: host [limbs]. psi_br: device [limbs][N].
+ */
+int pm_ntt_fwd(uint64_t *x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t *q,
+               const uint64_t *psi_br, pm_stream_t stream);
+
+/*
+ * In-place inverse: merged GS NTT (Alg. 6) with each butterfly output halved
+ * (Eq. 2), so the result includes the 1/N factor and pm_ntt_inv(pm_ntt_fwd(x))
+ * = x. x: device, bit-reversed in, normal out. psi_inv_br: device [limbs][N].
+ */
+int pm_ntt_inv(uint64_t *x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t *q,
+               const uint64_t *psi_inv_br, pm_stream_t stream);
+
+/*
+ * c = a (*) b (negacyclic) for every polynomial pair of the batch, by Eq. 2.
+ * a, b, c: device [limbs][polys_per_limb][N]; c may alias a or b.
+ * workspace: device, at least pm_polymul_workspace_bytes(N, limbs,
+ * polys_per_limb) bytes (may be NULL when that is 0); not preserved.
+ */
+int pm_polymul(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t N, size_t limbs,
+               size_t polys_per_limb, const uint64_t *q, const uint64_t *psi_br,
+               const uint64_t *psi_inv_br, void *workspace, pm_stream_t stream);
+
+/* Workspace bytes pm_polymul needs for this shape (0 if none). */
+size_t pm_polymul_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
+
+/*
+ * The plain per-stage path (the paper's global-memory radix-2 baseline):
+ * same result and arguments as pm_polymul, computed with one kernel launch per
+ * NTT stage (each launch covers a and b of every limb), one pointwise launch
+ * and one launch per inverse stage, every word read from and written to HBM
+ * at every stage. workspace: pm_polymul_stagewise_workspace_bytes() bytes.
+ */
+int pm_polymul_stagewise(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t N, size_t limbs,
+                         size_t polys_per_limb, const uint64_t *q, const uint64_t *psi_br,
+                         const uint64_t *psi_inv_br, void *workspace, pm_stream_t stream);
+size_t pm_polymul_stagewise_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
+
+/* ------------------------------------------------------------------- tuning
+ * Pass plan per (operation, N): an N-point transform is a column pass of
+ * R = N / 2^logc rows (in registers) followed by a row pass over rows of
+ * 2^logc words (in LDS); logc = log2 N is a single pass. op: 0 = pm_ntt_fwd,
+ * 1 = pm_ntt_inv, 2 = pm_polymul. logc = 0 restores the built-in default.
+ * pm_tune_set returns PM_EINVAL for a split the kernels do not implement
+ * (logc > 14, log2 N - logc > 5, or a column pass with fewer than 256 columns).
+ * The setting is process-wide and is read when a call is made.
+ */
+int pm_tune_set(int op, unsigned log2n, unsigned logc);
+int pm_tune_get(int op, unsigned log2n);   /* current logc, or PM_EINVAL */
+
+/* ---------------------------------------------------------------- host helpers
+ * Parameter generation on the host (no device work).
+ *
+ * pm_ntt_primes: the `count` largest primes q < 2^bits with q = 1 mod two_n, in
+ * descending order, written to out (host). Returns how many were found.
+ * pm_find_psi: psi = g^((q-1)/(2N)) for the smallest quadratic non-residue g
+ * (so psi^N = q-1); 0 if 2N does not divide q-1.
+ * pm_make_tables: psi_br[i] = psi^br(i), psi_inv_br[i] = psi^-br(i) (host arrays
+ * of N words). Returns PM_EINVAL if psi^N != q-1.
+ */
+size_t pm_ntt_primes(uint64_t two_n, unsigned bits, size_t count, uint64_t *out);
+uint64_t pm_find_psi(uint64_t q, size_t N);
+int pm_make_tables(uint64_t q, size_t N, uint64_t psi, uint64_t *psi_br, uint64_t *psi_inv_br);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

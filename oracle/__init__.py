@@ -44,6 +44,7 @@ def _declare(lib):
     u64, sz = ctypes.c_uint64, ctypes.c_size_t
     sig = {
         "or_mulmod": (u64, [u64, u64, u64]),
+        "or_mulmod_vec": (None, [_u64p, _u64p, _u64p, sz, u64]),
         "or_addmod": (u64, [u64, u64, u64]),
         "or_submod": (u64, [u64, u64, u64]),
         "or_powmod": (u64, [u64, u64, u64]),
@@ -108,9 +109,9 @@ class Oracle:
     def mulmod_vec(self, a, b, q):
         """Elementwise a*b mod q (the pm_barrett_mulmod definition)."""
         a, b = _u64(a), _u64(b)
-        f = self.lib.or_mulmod
-        return np.fromiter((f(int(x), int(y), q) for x, y in zip(a, b)),
-                           dtype=np.uint64, count=a.size)
+        c = np.empty_like(a)
+        self.lib.or_mulmod_vec(_p(a), _p(b), _p(c), a.size, q)
+        return c
 
     # -- polynomials -------------------------------------------------------
     def polymul_schoolbook(self, a, b, q):

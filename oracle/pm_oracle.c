@@ -12,7 +12,7 @@
  * Barrett reduction, no halving trick and no blocking or reordering.
  *
  * Functions and the passages they follow:
- *   or_mulmod / or_addmod / or_submod / or_powmod
+ *   or_mulmod / or_mulmod_vec / or_addmod / or_submod / or_powmod
  *       modular arithmetic of Z_q (Sec. III, opening definition of Z_m).
  *   or_polymul_schoolbook / or_polymul_coeff
  *       the negacyclic convolution, i.e. the product in Z_q[x]/(x^N + 1)
@@ -48,6 +48,11 @@ typedef unsigned __int128 u128;
 
 uint64_t or_mulmod(uint64_t a, uint64_t b, uint64_t q) {
     return (uint64_t)(((u128)a * (u128)b) % q);
+}
+
+/* c[i] = a[i]*b[i] mod q for i < n (elementwise definition of the product). */
+void or_mulmod_vec(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t n, uint64_t q) {
+    for (size_t i = 0; i < n; i++) c[i] = or_mulmod(a[i], b[i], q);
 }
 
 uint64_t or_addmod(uint64_t a, uint64_t b, uint64_t q) {

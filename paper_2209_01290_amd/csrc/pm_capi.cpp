@@ -1,0 +1,347 @@
+// Host runtime behind the C ABI of include/pm.h: argument validation, the
+// per-modulus Barrett constants of Alg. 4, the pass plan for each N, limb
+// chunking and kernel launches. Parameter helpers (primes, psi, twiddle
+// tables) are the library's own; they share nothing with the test oracle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pm.h"
+#include "pm_internal.hpp"
+#include "pm_plan.hpp"
+
+using namespace pm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+typedef unsigned __int128 u128;
+
+bool is_pow2(size_t n) { return n && !(n & (n - 1)); }
+unsigned log2u(size_t n) { unsigned l = 0; while (((size_t)1 << l) < n) ++l; return l; }
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+}  // namespace
+
+namespace pm {
+
+// Barrett constants of Alg. 4 for modulus q, in the form the kernels use
+// (see modarith.hpp): mu' = floor(2^(2m+1)/q) << (61-m) for m <= 61.
+bool make_mod(uint64_t q, Mod* M) {
+  if (q < 2 || (q >> 62) != 0) return false;
+  const int m = 64 - __builtin_clzll(q);
+  const u128 mu = (((u128)1) << (2 * m + 1)) / q;       // < 2^(m+2)
+  M->q = q;
+  M->half = (q >> 1) + 1;                                // (q+1)/2 for odd q
+  if (m <= 61) {
+    M->mu = (uint64_t)(mu << (61 - m));
+    M->t = 0;
+  } else {
+    M->mu = (uint64_t)mu;
+    M->t = 1;
+  }
+  if (m >= 34) { M->wide = 1; M->s1 = (uint32_t)(m - 34); }
+  else { M->wide = 0; M->s1 = (uint32_t)(m - 2); }
+  return true;
+}
+
+int mod_kind(const Mod& M) {
+  const int m = 64 - __builtin_clzll(M.q);
+  return (m >= 34 && m <= 61) ? KIND_WIDE : KIND_ANY;
+}
+
+}  // namespace pm
+
+namespace {
+
+struct Batch {
+  size_t N, limbs, polys;
+  unsigned log2n;
+  std::vector<Mod> mods;
+  int kind;
+};
+
+int check_batch(Batch* b, size_t N, size_t limbs, size_t polys, const uint64_t* q) {
+  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N))
+    return fail(PM_EINVAL, "N must be a power of two in [2, 2^17], got " + std::to_string(N));
+  if (limbs == 0 || polys == 0) return fail(PM_EINVAL, "limbs and polys_per_limb must be positive");
+  if (polys > 65535) return fail(PM_EINVAL, "polys_per_limb above 65535 is not supported");
+  if (!q) return fail(PM_EINVAL, "q (host array of limbs moduli) is null");
+  b->N = N; b->limbs = limbs; b->polys = polys; b->log2n = log2u(N);
+  b->mods.resize(limbs);
+  b->kind = KIND_WIDE;
+  for (size_t l = 0; l < limbs; ++l) {
+    const uint64_t ql = q[l];
+    if (!(ql & 1) || ql < 3 || (ql >> 62))
+      return fail(PM_EINVAL, "limb " + std::to_string(l) + ": q must be odd with 3 <= q < 2^62");
+    if ((ql - 1) % (2 * (uint64_t)N) != 0)
+      return fail(PM_EINVAL, "limb " + std::to_string(l) + ": 2N must divide q - 1");
+    make_mod(ql, &b->mods[l]);
+    if (mod_kind(b->mods[l]) != KIND_WIDE) b->kind = KIND_ANY;
+  }
+  return PM_OK;
+}
+
+int check_ptr(const void* p, const char* name) {
+  if (!p) return fail(PM_EINVAL, std::string(name) + " is null");
+  if (!aligned8(p)) return fail(PM_EINVAL, std::string(name) + " is not 8-byte aligned");
+  return PM_OK;
+}
+
+// Calls f(limb0, nlimbs, LimbSet) for consecutive chunks of at most MAXL limbs.
+template <class F>
+int for_chunks(const Batch& b, F f) {
+  LimbSet ls;
+  for (size_t l0 = 0; l0 < b.limbs; l0 += MAXL) {
+    const size_t nl = std::min((size_t)MAXL, b.limbs - l0);
+    std::memset(&ls, 0, sizeof(ls));
+    for (size_t i = 0; i < nl; ++i) ls.mod[i] = b.mods[l0 + i];
+    hipError_t e = f(l0, nl, ls);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  return PM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI ==
+
+extern "C" {
+
+const char* pm_last_error(void) { return g_err.c_str(); }
+
+int pm_barrett_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t n, uint64_t q,
+                      pm_stream_t stream) {
+  int rc;
+  if (n == 0) return fail(PM_EINVAL, "n must be positive");
+  if ((rc = check_ptr(a, "a")) || (rc = check_ptr(b, "b")) || (rc = check_ptr(c, "c"))) return rc;
+  Mod M;
+  if (!make_mod(q, &M)) return fail(PM_EINVAL, "q must satisfy 2 <= q < 2^62");
+  hipError_t e = launch_mulmod(a, b, c, n, M, mod_kind(M), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pm_barrett_mulmod launch");
+  g_err.clear();
+  return PM_OK;
+}
+
+static int ntt_common(uint64_t* x, size_t N, size_t limbs, size_t polys, const uint64_t* q,
+                      const uint64_t* tw, pm_stream_t stream, bool inv) {
+  Batch b;
+  int rc;
+  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr(x, "x")) || (rc = check_ptr(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
+  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n);
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
+    const size_t base = l0 * polys * N;
+    uint64_t* xs = x + base;
+    const uint64_t* t = tw + l0 * N;
+    RowArgs ra{xs, nullptr, xs, inv ? nullptr : t, inv ? t : nullptr, b.log2n, p.R, (uint32_t)polys,
+               (uint32_t)nl, &ls};
+    ColArgs ca{xs, xs, nullptr, nullptr, t, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+    hipError_t e;
+    if (!inv) {
+      if (p.R > 1 && (e = launch_col(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
+      return launch_row(p.logc, b.kind, ROW_FWD, ra, s);
+    }
+    if ((e = launch_row(p.logc, b.kind, ROW_INV, ra, s)) != hipSuccess) return e;
+    if (p.R > 1) return launch_col(p.logr, b.kind, true, ca, s);
+    return hipSuccess;
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
+}
+
+int pm_ntt_fwd(uint64_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t* q,
+               const uint64_t* psi_br, pm_stream_t stream) {
+  return ntt_common(x, N, limbs, polys_per_limb, q, psi_br, stream, false);
+}
+
+int pm_ntt_inv(uint64_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t* q,
+               const uint64_t* psi_inv_br, pm_stream_t stream) {
+  return ntt_common(x, N, limbs, polys_per_limb, q, psi_inv_br, stream, true);
+}
+
+size_t pm_polymul_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {
+  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N)) return 0;
+  const PassPlan p = plan_for(OP_POLYMUL, log2u(N));
+  return p.R > 1 ? N * limbs * polys_per_limb * sizeof(uint64_t) : 0;
+}
+
+int pm_polymul(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, size_t limbs,
+               size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br,
+               const uint64_t* psi_inv_br, void* workspace, pm_stream_t stream) {
+  Batch b;
+  int rc;
+  const size_t polys = polys_per_limb;
+  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr(a, "a")) || (rc = check_ptr(b_, "b")) || (rc = check_ptr(c, "c")) ||
+      (rc = check_ptr(psi_br, "psi_br")) || (rc = check_ptr(psi_inv_br, "psi_inv_br")))
+    return rc;
+  const PassPlan p = plan_for(OP_POLYMUL, b.log2n);
+  const bool square = (a == b_);
+  // The product is commutative: when c aliases b, swap so that c aliases a.
+  const uint64_t* A = a;
+  const uint64_t* B = b_;
+  if (c == B && c != A) std::swap(A, B);
+  uint64_t* ws = (uint64_t*)workspace;
+  if (p.R > 1 && !square) {
+    if ((rc = check_ptr(workspace, "workspace"))) return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
+    const size_t base = l0 * polys * N;
+    const uint64_t* tf = psi_br + l0 * N;
+    const uint64_t* ti = psi_inv_br + l0 * N;
+    if (p.R == 1) {
+      RowArgs ra{A + base, B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys, (uint32_t)nl, &ls};
+      return launch_row(p.logc, b.kind, ROW_MUL, ra, s);
+    }
+    // column stages of a (-> c) and b (-> workspace), fused rows, inverse columns of c
+    uint64_t* wb = square ? c + base : ws + base;
+    ColArgs cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
+               square ? 1u : 2u, &ls};
+    hipError_t e = launch_col(p.logr, b.kind, false, cf, s);
+    if (e != hipSuccess) return e;
+    RowArgs ra{c + base, wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl, &ls};
+    if ((e = launch_row(p.logc, b.kind, ROW_MUL, ra, s)) != hipSuccess) return e;
+    ColArgs ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+    return launch_col(p.logr, b.kind, true, ci, s);
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
+}
+
+size_t pm_polymul_stagewise_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {
+  return N * limbs * polys_per_limb * sizeof(uint64_t);
+}
+
+int pm_polymul_stagewise(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, size_t limbs,
+                         size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br,
+                         const uint64_t* psi_inv_br, void* workspace, pm_stream_t stream) {
+  Batch b;
+  int rc;
+  const size_t polys = polys_per_limb;
+  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr(a, "a")) || (rc = check_ptr(b_, "b")) || (rc = check_ptr(c, "c")) ||
+      (rc = check_ptr(psi_br, "psi_br")) || (rc = check_ptr(psi_inv_br, "psi_inv_br")))
+    return rc;
+  const bool square = (a == b_);
+  const uint64_t* A = a;
+  const uint64_t* B = b_;
+  if (c == B && c != A) std::swap(A, B);
+  if (!square && (rc = check_ptr(workspace, "workspace"))) return rc;
+  uint64_t* ws = (uint64_t*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
+    const size_t base = l0 * polys * N;
+    const uint64_t* tf = psi_br + l0 * N;
+    const uint64_t* ti = psi_inv_br + l0 * N;
+    uint64_t* wb = square ? c + base : ws + base;
+    hipError_t e;
+    for (unsigned lm = 0; lm < b.log2n; ++lm) {   // Alg. 5, stage m = 2^lm
+      ColArgs ca{lm == 0 ? A + base : c + base, c + base, lm == 0 ? B + base : wb, wb, tf, b.log2n,
+                 (uint32_t)polys, (uint32_t)nl, square ? 1u : 2u, &ls};
+      if ((e = launch_stage(b.kind, false, ca, lm, s)) != hipSuccess) return e;
+    }
+    if ((e = launch_pointwise(b.kind, c + base, wb, c + base, b.log2n, (uint32_t)polys, (uint32_t)nl, ls, s)) !=
+        hipSuccess)
+      return e;
+    for (int lm = (int)b.log2n - 1; lm >= 0; --lm) {   // Alg. 6, stage m = 2^lm, halved
+      ColArgs ca{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+      if ((e = launch_stage(b.kind, true, ca, (uint32_t)lm, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
+}
+
+// ------------------------------------------------------------ host helpers --
+
+static uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+static uint64_t powmod_h(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  for (b %= m; e; e >>= 1, b = mulmod_h(b, b, m))
+    if (e & 1) r = mulmod_h(r, b, m);
+  return r;
+}
+
+// Miller-Rabin with the seven Jaeschke/Sinclair bases, exact for 64-bit n.
+static bool probable_prime(uint64_t n) {
+  if (n < 4) return n >= 2;
+  if (!(n & 1)) return false;
+  uint64_t d = n - 1;
+  int s = __builtin_ctzll(d);
+  d >>= s;
+  static const uint64_t W[7] = {2, 325, 9375, 28178, 450775, 9780504, 1795265022};
+  for (uint64_t w : W) {
+    uint64_t a = w % n;
+    if (a == 0) continue;
+    uint64_t x = powmod_h(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s && comp; ++r) {
+      x = mulmod_h(x, x, n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+size_t pm_ntt_primes(uint64_t two_n, unsigned bits, size_t count, uint64_t* out) {
+  if (!two_n || bits < 2 || bits > 63 || !out) return 0;
+  const uint64_t lim = ((uint64_t)1 << bits) - 1;
+  size_t got = 0;
+  for (uint64_t k = (lim - 1) / two_n; k > 0 && got < count; --k) {
+    const uint64_t q = k * two_n + 1;
+    if (probable_prime(q)) out[got++] = q;
+  }
+  return got;
+}
+
+uint64_t pm_find_psi(uint64_t q, size_t N) {
+  if (N == 0 || q < 3 || (q - 1) % (2 * (uint64_t)N)) return 0;
+  for (uint64_t g = 2; g < q; ++g)
+    if (powmod_h(g, (q - 1) >> 1, q) == q - 1) return powmod_h(g, (q - 1) / (2 * (uint64_t)N), q);
+  return 0;
+}
+
+int pm_make_tables(uint64_t q, size_t N, uint64_t psi, uint64_t* psi_br, uint64_t* psi_inv_br) {
+  if (!is_pow2(N) || q < 3 || !psi_br || !psi_inv_br) return fail(PM_EINVAL, "bad arguments");
+  if (powmod_h(psi, N, q) != q - 1) return fail(PM_EINVAL, "psi^N != q - 1");
+  const unsigned bits = log2u(N);
+  // powers psi^e, e = 0..N-1, by repeated multiplication, then permuted
+  std::vector<uint64_t> pw(N), pwi(N);
+  const uint64_t psi_inv = powmod_h(psi, 2 * (uint64_t)N - 1, q);
+  pw[0] = pwi[0] = 1;
+  for (size_t e = 1; e < N; ++e) {
+    pw[e] = mulmod_h(pw[e - 1], psi, q);
+    pwi[e] = mulmod_h(pwi[e - 1], psi_inv, q);
+  }
+  for (size_t i = 0; i < N; ++i) {
+    size_t r = 0;
+    for (unsigned k = 0; k < bits; ++k) r |= ((i >> k) & 1) << (bits - 1 - k);
+    psi_br[i] = pw[r];
+    psi_inv_br[i] = pwi[r];
+  }
+  g_err.clear();
+  return PM_OK;
+}
+
+}  // extern "C"

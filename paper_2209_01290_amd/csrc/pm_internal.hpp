@@ -1,0 +1,52 @@
+// Declarations shared by the kernels file and the host runtime (not exported).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "modarith.hpp"
+
+namespace pm {
+
+// Moduli of up to MAXL limbs travel by value in the kernel arguments; larger
+// batches are launched in chunks of MAXL limbs.
+constexpr int MAXL = 64;
+struct LimbSet {
+  Mod mod[MAXL];
+};
+
+enum { ROW_FWD = 0, ROW_INV = 1, ROW_MUL = 2 };
+
+struct RowArgs {
+  const uint64_t* A;      // input rows (FWD/INV: in place with C allowed)
+  const uint64_t* B;      // second operand (MUL only)
+  uint64_t* C;            // output rows
+  const uint64_t* twf;    // psi_br, [limbs][N]
+  const uint64_t* twi;    // psi_inv_br, [limbs][N]
+  uint32_t log2n, R, polys, limbs;
+  const LimbSet* ls;
+};
+
+struct ColArgs {
+  const uint64_t* src0;
+  uint64_t* dst0;
+  const uint64_t* src1;   // second operand (nops == 2)
+  uint64_t* dst1;
+  const uint64_t* tw;     // [limbs][N]
+  uint32_t log2n, polys, limbs, nops;
+  const LimbSet* ls;
+};
+
+hipError_t launch_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t n, const Mod& M, int kind,
+                         hipStream_t s);
+hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s);
+#define PM_DECL_ROW(L) hipError_t launch_row_##L(int kind, int mode, const RowArgs& a, hipStream_t s);
+PM_DECL_ROW(1) PM_DECL_ROW(2) PM_DECL_ROW(3) PM_DECL_ROW(4) PM_DECL_ROW(5) PM_DECL_ROW(6) PM_DECL_ROW(7)
+PM_DECL_ROW(8) PM_DECL_ROW(9) PM_DECL_ROW(10) PM_DECL_ROW(11) PM_DECL_ROW(12) PM_DECL_ROW(13) PM_DECL_ROW(14)
+#undef PM_DECL_ROW
+hipError_t launch_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_t s);
+hipError_t launch_stage(int kind, bool inv, const ColArgs& a, uint32_t log2m, hipStream_t s);
+hipError_t launch_pointwise(int kind, const uint64_t* A, const uint64_t* B, uint64_t* C, uint32_t log2n,
+                            uint32_t polys, uint32_t limbs, const LimbSet& ls, hipStream_t s);
+
+}  // namespace pm

@@ -1,0 +1,220 @@
+"""ctypes binding of ``libpm.so`` (the C ABI declared in ``include/pm.h``).
+
+Argument marshalling only: each function has the name of its C entry point,
+takes torch tensors for device arrays (``torch.int64`` or ``torch.uint64``,
+contiguous, on a HIP device) and Python integers or sequences for host values,
+and raises ``PMError`` when the library returns an error code. Every step of
+the computation runs in the library's HIP kernels; there is no fallback: if
+``libpm.so`` is missing or cannot be loaded, calls raise.
+
+Streams: ``stream=None`` uses torch's current stream on the tensor's device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpm.so")
+
+PM_OK, PM_EINVAL, PM_EUNSUPPORTED, PM_ENOMEM, PM_EHIP = 0, -1, -2, -3, -4
+OP_NTT_FWD, OP_NTT_INV, OP_POLYMUL = 0, 1, 2
+
+_lock = threading.Lock()
+_lib = None
+
+
+class PMError(RuntimeError):
+    def __init__(self, code: int, func: str, msg: str):
+        super().__init__("%s failed (%d): %s" % (func, code, msg))
+        self.code = code
+
+
+def load():
+    """Load libpm.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        import torch  # noqa: F401  (loads libamdhip64 first)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpm.so is not built; run: python -m paper_2209_01290_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        sig = {
+            "pm_last_error": (ctypes.c_char_p, []),
+            "pm_barrett_mulmod": (i32, [vp, vp, vp, sz, u64, vp]),
+            "pm_ntt_fwd": (i32, [vp, sz, sz, sz, u64p, vp, vp]),
+            "pm_ntt_inv": (i32, [vp, sz, sz, sz, u64p, vp, vp]),
+            "pm_polymul": (i32, [vp, vp, vp, sz, sz, sz, u64p, vp, vp, vp, vp]),
+            "pm_polymul_workspace_bytes": (sz, [sz, sz, sz]),
+            "pm_polymul_stagewise": (i32, [vp, vp, vp, sz, sz, sz, u64p, vp, vp, vp, vp]),
+            "pm_polymul_stagewise_workspace_bytes": (sz, [sz, sz, sz]),
+            "pm_tune_set": (i32, [i32, ctypes.c_uint, ctypes.c_uint]),
+            "pm_tune_get": (i32, [i32, ctypes.c_uint]),
+            "pm_ntt_primes": (sz, [u64, ctypes.c_uint, sz, u64p]),
+            "pm_find_psi": (u64, [u64, sz]),
+            "pm_make_tables": (i32, [u64, sz, u64, u64p, u64p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+        return lib
+
+
+def exported_symbols():
+    """Names of the C entry points this binding declares."""
+    return ["pm_last_error", "pm_barrett_mulmod", "pm_ntt_fwd", "pm_ntt_inv", "pm_polymul",
+            "pm_polymul_workspace_bytes", "pm_polymul_stagewise",
+            "pm_polymul_stagewise_workspace_bytes", "pm_tune_set", "pm_tune_get",
+            "pm_ntt_primes", "pm_find_psi", "pm_make_tables"]
+
+
+def _check(rc: int, func: str):
+    if rc != PM_OK:
+        raise PMError(rc, func, load().pm_last_error().decode())
+
+
+def _dptr(t, name):
+    """Device pointer of a contiguous 64-bit tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live on a HIP device" % name)
+    if t.element_size() != 8 or t.dtype.is_floating_point:
+        raise TypeError("%s must be int64 or uint64" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def _stream(stream, like=None):
+    import torch
+    if stream is None:
+        dev = like.device if like is not None else None
+        return torch.cuda.current_stream(dev).cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _qarr(q, limbs):
+    qs = [int(x) for x in (q if hasattr(q, "__len__") else [q])]
+    if len(qs) != limbs:
+        raise ValueError("need %d moduli, got %d" % (limbs, len(qs)))
+    return (ctypes.c_uint64 * limbs)(*qs)
+
+
+# ------------------------------------------------------------ entry points --
+
+def pm_barrett_mulmod(a, b, c, q, n=None, stream=None):
+    n = a.numel() if n is None else n
+    _check(load().pm_barrett_mulmod(_dptr(a, "a"), _dptr(b, "b"), _dptr(c, "c"), n, int(q),
+                                    _stream(stream, a)), "pm_barrett_mulmod")
+
+
+def pm_ntt_fwd(x, N, limbs, polys_per_limb, q, psi_br, stream=None):
+    _check(load().pm_ntt_fwd(_dptr(x, "x"), N, limbs, polys_per_limb, _qarr(q, limbs),
+                             _dptr(psi_br, "psi_br"), _stream(stream, x)), "pm_ntt_fwd")
+
+
+def pm_ntt_inv(x, N, limbs, polys_per_limb, q, psi_inv_br, stream=None):
+    _check(load().pm_ntt_inv(_dptr(x, "x"), N, limbs, polys_per_limb, _qarr(q, limbs),
+                             _dptr(psi_inv_br, "psi_inv_br"), _stream(stream, x)), "pm_ntt_inv")
+
+
+def pm_polymul_workspace_bytes(N, limbs, polys_per_limb):
+    return int(load().pm_polymul_workspace_bytes(N, limbs, polys_per_limb))
+
+
+def pm_polymul_stagewise_workspace_bytes(N, limbs, polys_per_limb):
+    return int(load().pm_polymul_stagewise_workspace_bytes(N, limbs, polys_per_limb))
+
+
+def pm_polymul(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace=None, stream=None):
+    _check(load().pm_polymul(_dptr(a, "a"), _dptr(b, "b"), _dptr(c, "c"), N, limbs, polys_per_limb,
+                             _qarr(q, limbs), _dptr(psi_br, "psi_br"), _dptr(psi_inv_br, "psi_inv_br"),
+                             _dptr(workspace, "workspace"), _stream(stream, a)), "pm_polymul")
+
+
+def pm_polymul_stagewise(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace=None,
+                         stream=None):
+    _check(load().pm_polymul_stagewise(_dptr(a, "a"), _dptr(b, "b"), _dptr(c, "c"), N, limbs,
+                                       polys_per_limb, _qarr(q, limbs), _dptr(psi_br, "psi_br"),
+                                       _dptr(psi_inv_br, "psi_inv_br"), _dptr(workspace, "workspace"),
+                                       _stream(stream, a)), "pm_polymul_stagewise")
+
+
+def pm_tune_set(op, log2n, logc):
+    _check(load().pm_tune_set(op, log2n, logc), "pm_tune_set")
+
+
+def pm_tune_get(op, log2n):
+    r = load().pm_tune_get(op, log2n)
+    if r < 0:
+        _check(r, "pm_tune_get")
+    return r
+
+
+def pm_ntt_primes(N, count, bits=60):
+    out = (ctypes.c_uint64 * count)()
+    got = load().pm_ntt_primes(2 * N, bits, count, out)
+    return [int(out[i]) for i in range(got)]
+
+
+def pm_find_psi(q, N):
+    return int(load().pm_find_psi(q, N))
+
+
+def pm_make_tables(q, N, psi=None):
+    """(psi_br, psi_inv_br) as numpy uint64 arrays of N words."""
+    if psi is None:
+        psi = pm_find_psi(q, N)
+    fwd = np.empty(N, dtype=np.uint64)
+    inv = np.empty(N, dtype=np.uint64)
+    p = ctypes.POINTER(ctypes.c_uint64)
+    _check(load().pm_make_tables(q, N, psi, fwd.ctypes.data_as(p), inv.ctypes.data_as(p)),
+           "pm_make_tables")
+    return fwd, inv
+
+
+# ------------------------------------------------------------- helpers ----
+
+def to_device(arr: np.ndarray, device="cuda"):
+    """numpy uint64 -> torch int64 tensor on the device (same bits)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.uint64).view(np.int64)).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    """torch 64-bit tensor -> numpy uint64 (same bits)."""
+    return t.detach().to("cpu").contiguous().numpy().view(np.uint64)
+
+
+class Params:
+    """Moduli and device-resident twiddle tables for `limbs` limbs of size N.
+
+    Limb l uses the l-th largest prime q < 2^bits with q = 1 mod 2N (the
+    library's own generator) and psi from pm_find_psi."""
+
+    def __init__(self, N, limbs, bits=60, device="cuda", primes=None):
+        self.N, self.limbs = N, limbs
+        self.q = list(primes) if primes is not None else pm_ntt_primes(N, limbs, bits)
+        if len(self.q) != limbs:
+            raise ValueError("not enough primes")
+        fw = np.empty((limbs, N), dtype=np.uint64)
+        iv = np.empty((limbs, N), dtype=np.uint64)
+        for l, q in enumerate(self.q):
+            fw[l], iv[l] = pm_make_tables(q, N)
+        self.psi_br_host, self.psi_inv_br_host = fw, iv
+        self.psi_br = to_device(fw, device)
+        self.psi_inv_br = to_device(iv, device)

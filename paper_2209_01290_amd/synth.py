@@ -31,11 +31,14 @@ _M64 = (1 << 64) - 1
 
 
 def _mix(z: np.ndarray) -> np.ndarray:
-    z = z ^ (z >> np.uint64(30))
-    z = z * C1
-    z = z ^ (z >> np.uint64(27))
-    z = z * C2
-    return z ^ (z >> np.uint64(31))
+    z = np.array(z, dtype=np.uint64, copy=True)
+    with np.errstate(over="ignore"):
+        z ^= z >> np.uint64(30)
+        z *= C1
+        z ^= z >> np.uint64(27)
+        z *= C2
+        z ^= z >> np.uint64(31)
+    return z
 
 
 def _mix_int(z: int) -> int:

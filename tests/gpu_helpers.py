@@ -1,0 +1,69 @@
+"""Shared helpers for the GPU parity tests (operands, tables, oracle checks)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_2209_01290_amd import synth
+
+SEED = synth.SEED_BASE
+
+
+def operands(N, qs, polys, seed=SEED, request=0):
+    return synth.operands(seed, qs, polys, N, request=request)
+
+
+def oracle_tables(qs, N):
+    o = oracle.default()
+    fw = np.empty((len(qs), N), np.uint64)
+    iv = np.empty((len(qs), N), np.uint64)
+    for l, q in enumerate(qs):
+        fw[l], iv[l] = o.psi_tables(q, N)
+    return fw, iv
+
+
+def device_tables(qs, N):
+    """Tables built by the library's own host helper, uploaded."""
+    from paper_2209_01290_amd import lib
+    fw = np.empty((len(qs), N), np.uint64)
+    iv = np.empty((len(qs), N), np.uint64)
+    for l, q in enumerate(qs):
+        fw[l], iv[l] = lib.pm_make_tables(q, N)
+    return fw, iv, lib.to_device(fw), lib.to_device(iv)
+
+
+def oracle_polymul(a, b, qs, N, fw, iv):
+    o = oracle.default()
+    L, P = a.shape[0], a.shape[1]
+    c = np.empty_like(a)
+    for l in range(L):
+        for p in range(P):
+            c[l, p] = o.polymul_ntt(a[l, p], b[l, p], qs[l], fw[l], iv[l])
+    return c
+
+
+def oracle_ntt_fwd(x, qs, fw):
+    o = oracle.default()
+    y = np.empty_like(x)
+    for l in range(x.shape[0]):
+        for p in range(x.shape[1]):
+            y[l, p] = o.ntt_fwd(x[l, p], qs[l], fw[l])
+    return y
+
+
+def oracle_ntt_inv(x, qs, iv):
+    o = oracle.default()
+    y = np.empty_like(x)
+    for l in range(x.shape[0]):
+        for p in range(x.shape[1]):
+            y[l, p] = o.ntt_inv(x[l, p], qs[l], iv[l])
+    return y
+
+
+def first_mismatch(got, want):
+    bad = np.nonzero(got.reshape(-1) != want.reshape(-1))[0]
+    if bad.size == 0:
+        return None
+    i = int(bad[0])
+    return "%d mismatches, first at flat index %d: got %d want %d" % (
+        bad.size, i, int(got.reshape(-1)[i]), int(want.reshape(-1)[i]))

@@ -295,3 +295,16 @@ def pin_eval(o, seed=12):
 ALL_FAST = [pin_arith, pin_is_prime, pin_schoolbook_bruteforce, pin_closed_forms,
             pin_ring_laws, pin_ntt_eval, pin_ntt_invariants, pin_psi_weighted_cyclic,
             pin_coeff, pin_eval]
+
+
+def pin_mulmod_vec(o, seed=13):
+    """Elementwise product against Python integers."""
+    rng = random.Random(seed)
+    for q in [3, 12289, Q60, 2**62 - 57]:
+        a = [rng.randrange(q) for _ in range(200)] + [q - 1, 0, 1]
+        b = [rng.randrange(q) for _ in range(200)] + [q - 1, q - 1, q - 1]
+        got = o.mulmod_vec(np.array(a, np.uint64), np.array(b, np.uint64), q)
+        assert [int(x) for x in got] == [x * y % q for x, y in zip(a, b)]
+
+
+ALL_FAST.append(pin_mulmod_vec)

@@ -1,0 +1,103 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol the header
+declares, rejects invalid arguments before touching a device, and its host
+parameter helpers agree with the oracle. No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pm.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2209_01290_amd import lib
+    if not os.path.exists(lib.LIB_PATH):
+        pytest.fail("libpm.so is not built (python -m paper_2209_01290_amd.build)")
+    lib.load()
+    return lib
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = header_functions()
+    assert len(names) >= 12
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), "libpm.so does not export " + n
+    assert set(L.exported_symbols()) <= set(names)
+
+
+FAKE = ctypes.c_void_p(0x10000)      # never dereferenced: validation fails first
+
+
+def _rc(f, *args):
+    return f(*args)
+
+
+def test_invalid_arguments_rejected_on_host(L):
+    lib = L.load()
+    q = (ctypes.c_uint64 * 1)(0x0FFFFFFFFFFFC001)
+    # N not a power of two / out of range
+    for N in [0, 1, 3, 1000, 1 << 18]:
+        assert lib.pm_polymul(FAKE, FAKE, FAKE, N, 1, 1, q, FAKE, FAKE, FAKE, None) == L.PM_EINVAL
+        assert lib.pm_ntt_fwd(FAKE, N, 1, 1, q, FAKE, None) == L.PM_EINVAL
+        assert "N must be" in lib.pm_last_error().decode()
+    # even q, q >= 2^62, 2N not dividing q-1
+    for bad in [0x0FFFFFFFFFFFC000, (1 << 62) + 1, 0x0FFFFFFFFFFFC001 + 2]:
+        qb = (ctypes.c_uint64 * 1)(bad)
+        assert lib.pm_polymul(FAKE, FAKE, FAKE, 1024, 1, 1, qb, FAKE, FAKE, FAKE, None) == L.PM_EINVAL
+    # zero counts, null and misaligned pointers
+    assert lib.pm_polymul(FAKE, FAKE, FAKE, 1024, 0, 1, q, FAKE, FAKE, FAKE, None) == L.PM_EINVAL
+    assert lib.pm_polymul(None, FAKE, FAKE, 1024, 1, 1, q, FAKE, FAKE, FAKE, None) == L.PM_EINVAL
+    assert lib.pm_polymul(ctypes.c_void_p(0x10004), FAKE, FAKE, 1024, 1, 1, q, FAKE, FAKE, FAKE,
+                          None) == L.PM_EINVAL
+    assert "aligned" in lib.pm_last_error().decode()
+    # a 2-D split needs the workspace
+    assert lib.pm_polymul(FAKE, ctypes.c_void_p(0x20000), FAKE, 1 << 16, 1, 1,
+                          (ctypes.c_uint64 * 1)(0x0FFFFFFFFFFC0001), FAKE, FAKE, None, None) == L.PM_EINVAL
+    assert lib.pm_barrett_mulmod(FAKE, FAKE, FAKE, 0, 97, None) == L.PM_EINVAL
+    assert lib.pm_barrett_mulmod(FAKE, FAKE, FAKE, 8, 1 << 62, None) == L.PM_EINVAL
+    assert lib.pm_barrett_mulmod(FAKE, FAKE, FAKE, 8, 1, None) == L.PM_EINVAL
+
+
+def test_tuning_table(L):
+    for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
+        assert L.pm_tune_get(op, 16) == 12
+        with pytest.raises(L.PMError):
+            L.pm_tune_set(op, 16, 10)        # 64 rows: column radix above 2^5
+        with pytest.raises(L.PMError):
+            L.pm_tune_set(op, 12, 7)         # fewer than 256 columns
+        L.pm_tune_set(op, 16, 13)
+        assert L.pm_tune_get(op, 16) == 13
+        L.pm_tune_set(op, 16, 0)
+        assert L.pm_tune_get(op, 16) == 12
+
+
+def test_workspace_sizes(L):
+    assert L.pm_polymul_workspace_bytes(1024, 4, 2) == 0
+    assert L.pm_polymul_workspace_bytes(1 << 16, 48, 8) == (1 << 16) * 48 * 8 * 8
+    assert L.pm_polymul_stagewise_workspace_bytes(1 << 14, 32, 1) == (1 << 14) * 32 * 8
+
+
+@pytest.mark.parametrize("N,count", [(1024, 1), (1 << 14, 32), (1 << 16, 48), (1 << 17, 60)])
+def test_host_params_match_oracle(L, N, count):
+    o = oracle.default()
+    qs = L.pm_ntt_primes(N, count)
+    assert qs == o.ntt_primes(N, count)
+    for q in qs[:2]:
+        assert L.pm_find_psi(q, N) == o.find_psi(q, N)
+        if N <= 1 << 14:
+            f, i = L.pm_make_tables(q, N)
+            f2, i2 = o.psi_tables(q, N)
+            assert np.array_equal(f, f2) and np.array_equal(i, i2)
