@@ -1,0 +1,322 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: exact negacyclic polymul/s at N = 2^16 on one MI355X.
+
+Workload (one step): 48 RNS limbs, each with its own 60-bit prime
+q = 1 mod 2^17 (the 48 largest below 2^60), 8 independent polynomial pairs
+per limb, i.e. 384 products c = a (*) b in Z_q[x]/(x^65536 + 1), operands
+uniform in [0, q) from the seeded SplitMix64 generator. A step is one call of
+the batched entry point pm_polymul over the whole batch: forward merged CT
+NTT of a and b, pointwise product, halved merged GS inverse. Inputs, twiddle
+tables and outputs stay resident in HBM; the timed region holds only kernels.
+
+Reported beside the batched throughput:
+  plain       the same 384 products as 384 separate pm_polymul calls (one
+              launch sequence per product, no batching across products)
+  stagewise   pm_polymul_stagewise (one launch per NTT stage) on the batch
+  ntt_fwd     standalone forward transforms of the 384 a operands
+  roofline    the dominant kernel's live average duration (HIP events on its
+              own stream) against the VALU issue ceiling, with the HBM view
+  cpu_baseline  the CPU oracle on a bounded sample of the same products
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_LOG2, LIMBS, POLYS = 16, 48, 8
+SEED = 220901290 + 3
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one 32-bit VALU lane-op per
+# lane per cycle; HBM3E peak 8 TB/s.
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+PEAK_HBM_GBPS = 8000.0
+# VALU instructions per unit of the method's work, counted in the ISA of
+# register-resident loops over the device arithmetic (modarith.hpp).
+OPS_CT, OPS_GS, OPS_MUL = 37, 49, 25
+
+
+def alg_ops(name: str, N: int, limbs: int, polys: int) -> float:
+    """Algorithmic VALU lane-ops one launch of kernel `name` performs."""
+    if name.startswith("row_"):
+        logc = int(name.split("_c")[1])
+        C = 1 << logc
+        rows = limbs * polys * (N // C)
+        half = (C // 2) * logc                 # butterflies of one row transform
+        if name.startswith("row_mul"):
+            per = 2 * half * OPS_CT + C * OPS_MUL + half * OPS_GS
+        elif name.startswith("row_fwd"):
+            per = half * OPS_CT
+        else:
+            per = half * OPS_GS
+        return float(rows * per)
+    if name.startswith("col_"):
+        logr = int(name.split("_r")[1])
+        R = 1 << logr
+        cols = (N // R) * limbs * polys
+        nops = 2 if name.startswith("col_fwd") else 1
+        per = (R // 2) * logr * (OPS_CT if name.startswith("col_fwd") else OPS_GS)
+        return float(cols * nops * per)
+    return float("nan")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2209_01290_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".inc", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+def pct(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def cpu_baseline(N, qs, a_host, b_host, gpu_c, budget_s=12.0):
+    """The oracle (plain C, % reductions) on a bounded sample of the same
+    products, one product per thread over the host cores; checks the GPU's
+    outputs for the sampled pairs on the way."""
+    import oracle
+    o = oracle.default()
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    pairs = [(i % len(qs), (i // len(qs)) % a_host.shape[1]) for i in range(threads)]
+    tables = {}
+    for l, _ in pairs:
+        if l not in tables:
+            tables[l] = o.psi_tables(qs[l], N)
+    t0 = time.perf_counter()
+    l0, p0 = pairs[0]
+    c0 = o.polymul_ntt(a_host[l0, p0], b_host[l0, p0], qs[l0], *tables[l0])
+    t1 = time.perf_counter() - t0
+    if not np.array_equal(c0, gpu_c[l0, p0]):
+        raise SystemExit("GPU output differs from the oracle on limb %d pair %d" % (l0, p0))
+    reps = max(1, int(budget_s / max(t1, 1e-6) / 1.5))
+
+    def work(k):
+        l, p = pairs[k]
+        for _ in range(reps):
+            c = o.polymul_ntt(a_host[l, p], b_host[l, p], qs[l], *tables[l])
+        return k, c
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        outs = list(ex.map(work, range(threads)))
+    wall = time.perf_counter() - t0
+    for k, c in outs:
+        l, p = pairs[k]
+        if not np.array_equal(c, gpu_c[l, p]):
+            raise SystemExit("GPU output differs from the oracle on limb %d pair %d" % (l, p))
+    return {"value": threads * reps / wall, "unit": "polymul/s", "cores": threads, "kind": "oracle",
+            "sample": "%d products of the N=2^16 workload (%d per thread, %d threads, limbs %s), "
+                      "textbook merged NTTs with %% reductions, gcc -O2; single-thread %.1f ms/product"
+                      % (threads * reps, reps, threads, sorted(set(l for l, _ in pairs)), 1e3 * t1)}
+
+
+def copy_probe(torch, dev, steps):
+    """Plain device-to-device copies of 1 GiB: a kernel of known HBM traffic
+    (1 GiB read + 1 GiB written per launch) for scaling rocprofv3 counters."""
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({"copy_probe_bytes_read": 1 << 30, "copy_probe_bytes_written": 1 << 30,
+                      "ms_per_copy": round(ms, 4), "GBps_read_plus_write": round(2 * (1 << 30) / ms / 1e6, 1)}),
+          flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="only the batched step")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time only plain device copies of 1 GiB (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the workload's limbs are independent and would be "
+              "split across GPUs with no communication; run it with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2209_01290_amd import lib, synth
+
+    lib.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_probe:
+        copy_probe(torch, dev, args.steps)
+        return
+    N = 1 << N_LOG2
+    prm = lib.Params(N, LIMBS, device=dev)
+    qs = prm.q
+    a_host, b_host = synth.operands(SEED, qs, POLYS, N)
+    da, db = lib.to_device(a_host, dev), lib.to_device(b_host, dev)
+    dc = torch.empty_like(da)
+    ws_bytes = lib.pm_polymul_workspace_bytes(N, LIMBS, POLYS)
+    ws = torch.empty(max(ws_bytes // 8, 1), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        lib.pm_polymul(da, db, dc, N, LIMBS, POLYS, qs, prm.psi_br, prm.psi_inv_br, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K batched steps, kernels timed live with HIP events
+    lib.pm_prof_read(reset=True)
+    lib.pm_prof_enable(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for k in range(args.steps):
+        step()
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    lib.pm_prof_enable(False)
+    kern = lib.pm_prof_read(reset=True)
+    total_ms = evs[0].elapsed_time(evs[-1])
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    products = LIMBS * POLYS
+    value = products * args.steps / (total_ms / 1e3)
+
+    # ---- roofline of the dominant kernel
+    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
+    launches, dom_ms = kern[dom]
+    dom_avg_s = dom_ms / launches / 1e3
+    ops = alg_ops(dom, N, LIMBS, POLYS)
+    achieved = ops / dom_avg_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
+                "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                "traffic": measured_traffic(dom), "kernel": dom,
+                "kernel_avg_ms": round(dom_avg_s * 1e3, 4),
+                "alg_ops_per_launch": ops}
+    # HBM view of the whole step: operands and result once, tables once per limb
+    b_alg = products * 24 * N + LIMBS * 16 * N
+    hbm = {"alg_bytes_per_step": b_alg,
+           "achieved_GBps": round(b_alg * args.steps / (total_ms / 1e3) / 1e9, 1),
+           "peak_GBps": PEAK_HBM_GBPS}
+    hbm["frac"] = round(hbm["achieved_GBps"] / PEAK_HBM_GBPS, 4)
+
+    out = {
+        "metric": "negacyclic polymul/s & % HBM roofline, N=2^16 q<2^60; batched vs plain; p99",
+        "value": round(value, 1), "unit": "polymul/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "N=2^16 negacyclic polymul, 48 limbs x 8 pairs (384 products), "
+                               "48 largest 60-bit primes q = 1 mod 2^17, uniform operands",
+                   "N": N, "limbs": LIMBS, "polys_per_limb": POLYS, "path": "pm_polymul (batched)",
+                   "pass_plan_logc": lib.pm_tune_get(lib.OP_POLYMUL, N_LOG2)},
+        "latency_ms": {"p50": round(pct(step_ms, 50), 4), "p99": round(pct(step_ms, 99), 4),
+                       "unit": "per batched step of 384 products"},
+        "roofline": roofline,
+        "hbm_roofline": hbm,
+        "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(kern.items())},
+    }
+
+    if not args.no_extra:
+        # plain: one launch sequence per product
+        plain_ms = []
+        for _ in range(1 + args.plain_steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(products + 1)]
+            ev[0].record(stream)
+            i = 0
+            for l in range(LIMBS):
+                for p in range(POLYS):
+                    lib.pm_polymul(da[l, p], db[l, p], dc[l, p], N, 1, 1, [qs[l]], prm.psi_br[l],
+                                   prm.psi_inv_br[l], ws)
+                    i += 1
+                    ev[i].record(stream)
+            torch.cuda.synchronize()
+            plain_ms.append([ev[k].elapsed_time(ev[k + 1]) for k in range(products)])
+        per = [x for run in plain_ms[1:] for x in run]
+        out["plain"] = {"value": round(1e3 / (sum(per) / len(per)), 1), "unit": "polymul/s",
+                        "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
+                        "what": "384 separate pm_polymul calls per step (one launch sequence each)"}
+        out["batched_over_plain"] = round(value / out["plain"]["value"], 3)
+        # stagewise: one launch per NTT stage, whole batch per launch
+        sws = torch.empty(lib.pm_polymul_stagewise_workspace_bytes(N, LIMBS, POLYS) // 8,
+                          dtype=torch.int64, device=dev)
+        for _ in range(2):
+            lib.pm_polymul_stagewise(da, db, dc, N, LIMBS, POLYS, qs, prm.psi_br, prm.psi_inv_br, sws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = 3
+        for _ in range(reps):
+            lib.pm_polymul_stagewise(da, db, dc, N, LIMBS, POLYS, qs, prm.psi_br, prm.psi_inv_br, sws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["stagewise"] = {"value": round(products * reps / (e0.elapsed_time(e1) / 1e3), 1),
+                            "unit": "polymul/s", "what": "pm_polymul_stagewise, one launch per stage"}
+        del sws
+        # standalone forward NTT of the 384 a operands
+        x = da.clone()
+        for _ in range(3):
+            lib.pm_ntt_fwd(x, N, LIMBS, POLYS, qs, prm.psi_br)
+        e0.record(stream)
+        reps = 20
+        for _ in range(reps):
+            lib.pm_ntt_fwd(x, N, LIMBS, POLYS, qs, prm.psi_br)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["ntt_fwd"] = {"value": round(products * reps / (e0.elapsed_time(e1) / 1e3), 1),
+                          "unit": "NTT/s", "what": "pm_ntt_fwd over the 384 a operands"}
+        # restore the batched result for the CPU check below
+        step()
+        torch.cuda.synchronize()
+
+    if not args.no_cpu:
+        gpu_c = lib.to_host(dc).reshape(a_host.shape)
+        out["cpu_baseline"] = cpu_baseline(N, qs, a_host, b_host, gpu_c)
+        out["gpu_over_cpu"] = round(value / out["cpu_baseline"]["value"], 1)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,6 +118,23 @@ size_t pm_polymul_stagewise_workspace_bytes(size_t N, size_t limbs, size_t polys
 int pm_tune_set(int op, unsigned log2n, unsigned logc);
 int pm_tune_get(int op, unsigned log2n);   /* current logc, or PM_EINVAL */
 
+/* ------------------------------------------------------------- kernel timing
+ * While enabled, every kernel the library launches is bracketed by two HIP
+ * events recorded on the launch's own stream (the measurement a profiler
+ * would make, taken live). pm_prof_read waits for the recorded events and
+ * writes per-kernel totals (launch count and summed milliseconds) to out
+ * (host, cap entries); *n receives the number of distinct kernels. reset != 0
+ * discards the records afterwards. Recording costs two event records per
+ * launch; leave it disabled outside measurements.
+ */
+typedef struct {
+  char name[48];
+  uint64_t launches;
+  double total_ms;
+} pm_prof_entry;
+int pm_prof_enable(int on);
+int pm_prof_read(pm_prof_entry *out, size_t cap, size_t *n, int reset);
+
 /* ---------------------------------------------------------------- host helpers
  * Parameter generation on the host (no device work).
  *

@@ -13,6 +13,7 @@
 #include "../../include/pm.h"
 #include "pm_internal.hpp"
 #include "pm_plan.hpp"
+#include "pm_prof.hpp"
 
 using namespace pm;
 
@@ -102,6 +103,49 @@ int check_ptr(const void* p, const char* name) {
   return PM_OK;
 }
 
+// Launch wrappers that name each kernel for the event timer.
+const char* row_name(int mode, int logc) {
+  static std::vector<std::string> names = [] {
+    std::vector<std::string> v;
+    const char* m[3] = {"row_fwd_c", "row_inv_c", "row_mul_c"};
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c));
+    return v;
+  }();
+  return names[mode * 15 + logc].c_str();
+}
+
+const char* col_name(bool inv, int logr) {
+  static std::vector<std::string> names = [] {
+    std::vector<std::string> v;
+    for (int i = 0; i < 2; ++i)
+      for (int r = 0; r <= 5; ++r) v.push_back(std::string(i ? "col_inv_r" : "col_fwd_r") + std::to_string(r));
+    return v;
+  }();
+  return names[(inv ? 6 : 0) + logr].c_str();
+}
+
+hipError_t run_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s) {
+  ProfScope ps(s, row_name(mode, logc));
+  return launch_row(logc, kind, mode, a, s);
+}
+
+hipError_t run_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_t s) {
+  ProfScope ps(s, col_name(inv, logr));
+  return launch_col(logr, kind, inv, a, s);
+}
+
+hipError_t run_stage(int kind, bool inv, const ColArgs& a, uint32_t log2m, hipStream_t s) {
+  ProfScope ps(s, inv ? "stage_inv" : "stage_fwd");
+  return launch_stage(kind, inv, a, log2m, s);
+}
+
+hipError_t run_pointwise(int kind, const uint64_t* A, const uint64_t* B, uint64_t* C, uint32_t log2n,
+                         uint32_t polys, uint32_t limbs, const LimbSet& ls, hipStream_t s) {
+  ProfScope ps(s, "pointwise");
+  return launch_pointwise(kind, A, B, C, log2n, polys, limbs, ls, s);
+}
+
 // Calls f(limb0, nlimbs, LimbSet) for consecutive chunks of at most MAXL limbs.
 template <class F>
 int for_chunks(const Batch& b, F f) {
@@ -131,7 +175,11 @@ int pm_barrett_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t 
   if ((rc = check_ptr(a, "a")) || (rc = check_ptr(b, "b")) || (rc = check_ptr(c, "c"))) return rc;
   Mod M;
   if (!make_mod(q, &M)) return fail(PM_EINVAL, "q must satisfy 2 <= q < 2^62");
-  hipError_t e = launch_mulmod(a, b, c, n, M, mod_kind(M), (hipStream_t)stream);
+  hipError_t e;
+  {
+    ProfScope ps((hipStream_t)stream, "mulmod");
+    e = launch_mulmod(a, b, c, n, M, mod_kind(M), (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "pm_barrett_mulmod launch");
   g_err.clear();
   return PM_OK;
@@ -154,11 +202,11 @@ static int ntt_common(uint64_t* x, size_t N, size_t limbs, size_t polys, const u
     ColArgs ca{xs, xs, nullptr, nullptr, t, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
     hipError_t e;
     if (!inv) {
-      if (p.R > 1 && (e = launch_col(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
-      return launch_row(p.logc, b.kind, ROW_FWD, ra, s);
+      if (p.R > 1 && (e = run_col(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
+      return run_row(p.logc, b.kind, ROW_FWD, ra, s);
     }
-    if ((e = launch_row(p.logc, b.kind, ROW_INV, ra, s)) != hipSuccess) return e;
-    if (p.R > 1) return launch_col(p.logr, b.kind, true, ca, s);
+    if ((e = run_row(p.logc, b.kind, ROW_INV, ra, s)) != hipSuccess) return e;
+    if (p.R > 1) return run_col(p.logr, b.kind, true, ca, s);
     return hipSuccess;
   });
   if (rc == PM_OK) g_err.clear();
@@ -208,18 +256,18 @@ int pm_polymul(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, siz
     const uint64_t* ti = psi_inv_br + l0 * N;
     if (p.R == 1) {
       RowArgs ra{A + base, B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys, (uint32_t)nl, &ls};
-      return launch_row(p.logc, b.kind, ROW_MUL, ra, s);
+      return run_row(p.logc, b.kind, ROW_MUL, ra, s);
     }
     // column stages of a (-> c) and b (-> workspace), fused rows, inverse columns of c
     uint64_t* wb = square ? c + base : ws + base;
     ColArgs cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
                square ? 1u : 2u, &ls};
-    hipError_t e = launch_col(p.logr, b.kind, false, cf, s);
+    hipError_t e = run_col(p.logr, b.kind, false, cf, s);
     if (e != hipSuccess) return e;
     RowArgs ra{c + base, wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl, &ls};
-    if ((e = launch_row(p.logc, b.kind, ROW_MUL, ra, s)) != hipSuccess) return e;
+    if ((e = run_row(p.logc, b.kind, ROW_MUL, ra, s)) != hipSuccess) return e;
     ColArgs ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
-    return launch_col(p.logr, b.kind, true, ci, s);
+    return run_col(p.logr, b.kind, true, ci, s);
   });
   if (rc == PM_OK) g_err.clear();
   return rc;
@@ -255,14 +303,14 @@ int pm_polymul_stagewise(const uint64_t* a, const uint64_t* b_, uint64_t* c, siz
     for (unsigned lm = 0; lm < b.log2n; ++lm) {   // Alg. 5, stage m = 2^lm
       ColArgs ca{lm == 0 ? A + base : c + base, c + base, lm == 0 ? B + base : wb, wb, tf, b.log2n,
                  (uint32_t)polys, (uint32_t)nl, square ? 1u : 2u, &ls};
-      if ((e = launch_stage(b.kind, false, ca, lm, s)) != hipSuccess) return e;
+      if ((e = run_stage(b.kind, false, ca, lm, s)) != hipSuccess) return e;
     }
-    if ((e = launch_pointwise(b.kind, c + base, wb, c + base, b.log2n, (uint32_t)polys, (uint32_t)nl, ls, s)) !=
+    if ((e = run_pointwise(b.kind, c + base, wb, c + base, b.log2n, (uint32_t)polys, (uint32_t)nl, ls, s)) !=
         hipSuccess)
       return e;
     for (int lm = (int)b.log2n - 1; lm >= 0; --lm) {   // Alg. 6, stage m = 2^lm, halved
       ColArgs ca{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
-      if ((e = launch_stage(b.kind, true, ca, (uint32_t)lm, s)) != hipSuccess) return e;
+      if ((e = run_stage(b.kind, true, ca, (uint32_t)lm, s)) != hipSuccess) return e;
     }
     return hipSuccess;
   });

@@ -27,6 +27,10 @@ _lock = threading.Lock()
 _lib = None
 
 
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
 class PMError(RuntimeError):
     def __init__(self, code: int, func: str, msg: str):
         super().__init__("%s failed (%d): %s" % (func, code, msg))
@@ -59,6 +63,8 @@ def load():
             "pm_ntt_primes": (sz, [u64, ctypes.c_uint, sz, u64p]),
             "pm_find_psi": (u64, [u64, sz]),
             "pm_make_tables": (i32, [u64, sz, u64, u64p, u64p]),
+            "pm_prof_enable": (i32, [i32]),
+            "pm_prof_read": (i32, [ctypes.POINTER(ProfEntry), sz, ctypes.POINTER(sz), i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -73,7 +79,7 @@ def exported_symbols():
     return ["pm_last_error", "pm_barrett_mulmod", "pm_ntt_fwd", "pm_ntt_inv", "pm_polymul",
             "pm_polymul_workspace_bytes", "pm_polymul_stagewise",
             "pm_polymul_stagewise_workspace_bytes", "pm_tune_set", "pm_tune_get",
-            "pm_ntt_primes", "pm_find_psi", "pm_make_tables"]
+            "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read"]
 
 
 def _check(rc: int, func: str):
@@ -163,6 +169,21 @@ def pm_tune_get(op, log2n):
     if r < 0:
         _check(r, "pm_tune_get")
     return r
+
+
+def pm_prof_enable(on=True):
+    _check(load().pm_prof_enable(1 if on else 0), "pm_prof_enable")
+
+
+def pm_prof_read(reset=True):
+    """{kernel name: (launches, total_ms)} for launches timed since the last reset."""
+    lib = load()
+    cap = 64
+    buf = (ProfEntry * cap)()
+    n = ctypes.c_size_t(0)
+    _check(lib.pm_prof_read(buf, cap, ctypes.byref(n), 1 if reset else 0), "pm_prof_read")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+            for i in range(min(n.value, cap))}
 
 
 def pm_ntt_primes(N, count, bits=60):
