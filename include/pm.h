@@ -106,6 +106,49 @@ int pm_polymul_stagewise(const uint64_t *a, const uint64_t *b, uint64_t *c, size
                          const uint64_t *psi_inv_br, void *workspace, pm_stream_t stream);
 size_t pm_polymul_stagewise_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
 
+/* ---------------------------------------------------------- batched jobs
+ * A job is `count` polynomial pairs sharing N = 2^log2n and modulus q:
+ * c[i] = a[i] (*) b[i] for i < count, each array count*N words (device).
+ * A batch mixes jobs of any N (2..2^17) and modulus; an RNS product of L
+ * limbs is L jobs. Each pass of Eq. 2 (forward columns, fused rows, inverse
+ * columns) is one kernel launch over the work of all jobs of the batch.
+ * Per job, c may alias a or b; buffers of different jobs must not overlap.
+ */
+typedef struct {
+  uint32_t log2n;               /* N = 2^log2n, 1 <= log2n <= 17 */
+  uint32_t count;               /* polynomial pairs of this job */
+  uint64_t q;                   /* modulus, as for pm_polymul */
+  const uint64_t *psi_br;       /* device, N words */
+  const uint64_t *psi_inv_br;   /* device, N words */
+  const uint64_t *a, *b;        /* device, count*N words each */
+  uint64_t *c;                  /* device, count*N words */
+} pm_job;
+
+/*
+ * One-shot form: validates the jobs, uploads a job table into `workspace`
+ * (device, 256-byte aligned, at least pm_polymul_jobs_workspace_bytes()
+ * bytes; it also holds intermediates) and enqueues the passes on `stream`.
+ * The host job array may be reused as soon as the call returns.
+ */
+size_t pm_polymul_jobs_workspace_bytes(const pm_job *jobs, size_t njobs); /* 0 if invalid */
+int pm_polymul_jobs(const pm_job *jobs, size_t njobs, void *workspace, size_t workspace_bytes,
+                    pm_stream_t stream);
+
+/*
+ * Plan form: pm_plan_create validates the jobs, allocates the job table and
+ * intermediates on the current device (pm_plan_device_bytes() bytes) and
+ * captures the passes into a HIP graph; pm_plan_launch replays the graph on
+ * `stream` (one graph launch per batch). The jobs' buffers must stay valid and
+ * are read again at every launch. flags: PM_PLAN_NO_GRAPH launches the kernels
+ * directly instead. Pass plans (pm_tune_set) are read at creation.
+ */
+typedef struct pm_plan pm_plan;
+#define PM_PLAN_NO_GRAPH 1u
+int pm_plan_create(pm_plan **plan, const pm_job *jobs, size_t njobs, unsigned flags);
+int pm_plan_launch(pm_plan *plan, pm_stream_t stream);
+int pm_plan_destroy(pm_plan *plan);   /* waits for the device before freeing */
+size_t pm_plan_device_bytes(const pm_plan *plan);
+
 /* ------------------------------------------------------------------- tuning
  * Pass plan per (operation, N): an N-point transform is a column pass of
  * R = N / 2^logc rows (in registers) followed by a row pass over rows of

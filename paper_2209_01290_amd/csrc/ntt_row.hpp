@@ -1,0 +1,63 @@
+// One row task of the row pass (see ntt_device.hpp), shared by the batch
+// kernels (row_kernel.inc) and the job-table kernels (pm_jobs.hip).
+//
+//   ROW_FWD  the last c stages of Alg. 5 on one row, in place
+//   ROW_INV  the first c stages of Alg. 6 (halved butterflies), in place
+//   ROW_MUL  the row of a forward, the row of b forward, pointwise product
+//            mod q, inverse; with R = 1 this is all of Eq. 2 for one pair
+//   ROW_SQR  as ROW_MUL with b = a (one forward transform)
+#pragma once
+#include "ntt_device.hpp"
+#include "pm_internal.hpp"
+
+namespace pm {
+
+template <int LOGC, int KIND, int MODE>
+__device__ __forceinline__ void row_task(const uint64_t* A, const uint64_t* B, uint64_t* Cout,
+                                         const uint64_t* tf, const uint64_t* ti,
+                                         uint32_t Rr, bool active, const Mod& M, uint64_t* lds, uint32_t t) {
+  using G = RowGeom<LOGC>;
+  uint64_t x[G::E];
+#pragma unroll
+  for (int j = 0; j < G::E; ++j) x[j] = 0;
+  if (MODE == ROW_FWD) {
+    if (active) gmem_get<LOGC, 0>(A, x, t);
+    fwd_rounds<LOGC, KIND>(lds, x, t, tf, Rr, M);
+    if (active) gmem_put<LOGC, G::NR - 1>(Cout, x, t);
+  } else if (MODE == ROW_INV) {
+    if (active) gmem_get<LOGC, G::NR - 1>(A, x, t);
+    inv_rounds<LOGC, KIND>(lds, x, t, ti, Rr, M);
+    if (active) gmem_put<LOGC, 0>(Cout, x, t);
+  } else if (MODE == ROW_MUL) {
+    if (active) gmem_get<LOGC, 0>(A, x, t);
+    fwd_rounds<LOGC, KIND>(lds, x, t, tf, Rr, M);
+    // keep the scheduler from overlapping the two transforms (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t y[G::E];
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) y[j] = 0;
+    if (active) gmem_get<LOGC, 0>(B, y, t);
+    fwd_rounds<LOGC, KIND>(lds, y, t, tf, Rr, M);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) x[j] = mulmod<KIND>(x[j], y[j], M);
+    inv_rounds<LOGC, KIND>(lds, x, t, ti, Rr, M);
+    if (active) gmem_put<LOGC, 0>(Cout, x, t);
+  } else {  // ROW_SQR: a == b, one forward transform
+    if (active) gmem_get<LOGC, 0>(A, x, t);
+    fwd_rounds<LOGC, KIND>(lds, x, t, tf, Rr, M);
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) x[j] = mulmod<KIND>(x[j], x[j], M);
+    inv_rounds<LOGC, KIND>(lds, x, t, ti, Rr, M);
+    if (active) gmem_put<LOGC, 0>(Cout, x, t);
+  }
+}
+
+// Register budget: transforms keep 4 waves per SIMD (<= 128 VGPRs); the fused
+// product holds a second row of 16 words and gets 3 waves per SIMD.
+template <int MODE>
+struct RowWaves {
+  static constexpr int value = MODE == ROW_MUL ? 3 : 4;   // ROW_SQR holds one row
+};
+
+}  // namespace pm

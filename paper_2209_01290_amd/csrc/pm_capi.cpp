@@ -60,6 +60,11 @@ bool make_mod(uint64_t q, Mod* M) {
   return true;
 }
 
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
 int mod_kind(const Mod& M) {
   const int m = 64 - __builtin_clzll(M.q);
   return (m >= 34 && m <= 61) ? KIND_WIDE : KIND_ANY;
@@ -107,8 +112,8 @@ int check_ptr(const void* p, const char* name) {
 const char* row_name(int mode, int logc) {
   static std::vector<std::string> names = [] {
     std::vector<std::string> v;
-    const char* m[3] = {"row_fwd_c", "row_inv_c", "row_mul_c"};
-    for (int i = 0; i < 3; ++i)
+    const char* m[4] = {"row_fwd_c", "row_inv_c", "row_mul_c", "row_sqr_c"};
+    for (int i = 0; i < 4; ++i)
       for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c));
     return v;
   }();
@@ -255,8 +260,9 @@ int pm_polymul(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, siz
     const uint64_t* tf = psi_br + l0 * N;
     const uint64_t* ti = psi_inv_br + l0 * N;
     if (p.R == 1) {
-      RowArgs ra{A + base, B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys, (uint32_t)nl, &ls};
-      return run_row(p.logc, b.kind, ROW_MUL, ra, s);
+      RowArgs ra{A + base, square ? nullptr : B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys,
+                 (uint32_t)nl, &ls};
+      return run_row(p.logc, b.kind, square ? ROW_SQR : ROW_MUL, ra, s);
     }
     // column stages of a (-> c) and b (-> workspace), fused rows, inverse columns of c
     uint64_t* wb = square ? c + base : ws + base;
@@ -264,8 +270,9 @@ int pm_polymul(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, siz
                square ? 1u : 2u, &ls};
     hipError_t e = run_col(p.logr, b.kind, false, cf, s);
     if (e != hipSuccess) return e;
-    RowArgs ra{c + base, wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl, &ls};
-    if ((e = run_row(p.logc, b.kind, ROW_MUL, ra, s)) != hipSuccess) return e;
+    RowArgs ra{c + base, square ? nullptr : wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl,
+               &ls};
+    if ((e = run_row(p.logc, b.kind, square ? ROW_SQR : ROW_MUL, ra, s)) != hipSuccess) return e;
     ColArgs ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
     return run_col(p.logr, b.kind, true, ci, s);
   });

@@ -15,7 +15,7 @@ struct LimbSet {
   Mod mod[MAXL];
 };
 
-enum { ROW_FWD = 0, ROW_INV = 1, ROW_MUL = 2 };
+enum { ROW_FWD = 0, ROW_INV = 1, ROW_MUL = 2, ROW_SQR = 3 };
 
 struct RowArgs {
   const uint64_t* A;      // input rows (FWD/INV: in place with C allowed)
@@ -48,5 +48,11 @@ hipError_t launch_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_
 hipError_t launch_stage(int kind, bool inv, const ColArgs& a, uint32_t log2m, hipStream_t s);
 hipError_t launch_pointwise(int kind, const uint64_t* A, const uint64_t* B, uint64_t* C, uint32_t log2n,
                             uint32_t polys, uint32_t limbs, const LimbSet& ls, hipStream_t s);
+
+// Job-table passes (pm_jobs.hip): phase PH_COLF / PH_ROW / PH_COLI, the row
+// phase split by maximal row length (12, 13 or 14).
+struct JobDev;
+hipError_t launch_jobs(int phase, int maxlogc, int kind, const JobDev* jobs, const uint32_t* item_job,
+                       uint32_t nitems, hipStream_t s);
 
 }  // namespace pm

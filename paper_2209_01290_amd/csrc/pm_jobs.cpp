@@ -1,0 +1,295 @@
+// Batched entry points over a job table (include/pm.h: pm_plan_*,
+// pm_polymul_jobs). A job is `count` polynomial pairs sharing N and q; a
+// batch mixes jobs of any N and modulus. Every job runs the three passes of
+// Eq. 2 (forward columns, fused rows, inverse columns), each pass being one
+// launch over the work items of all jobs, so a whole batch is three (or up to
+// five, with tuned long rows) kernel launches whatever its mix.
+//
+// Device blob layout (built on the host, one copy to the device):
+//   [JobDev x njobs][item->job maps: colf, row12, row13, row14, coli]
+//   [pad to 256 B][b's column outputs of the two-pass jobs]
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pm.h"
+#include "pm_internal.hpp"
+#include "pm_jobs.hpp"
+#include "pm_plan.hpp"
+#include "pm_prof.hpp"
+
+namespace pm {
+bool make_mod(uint64_t q, Mod* M);
+int mod_kind(const Mod& M);
+int set_error(int code, const std::string& msg);
+}  // namespace pm
+
+using namespace pm;
+
+namespace {
+
+constexpr int NGROUP = 5;   // colf, row12, row13, row14, coli
+enum { G_COLF = 0, G_ROW12 = 1, G_ROW13 = 2, G_ROW14 = 3, G_COLI = 4 };
+
+struct Layout {
+  std::vector<JobDev> jobs;            // device pointers patched once the base is known
+  std::vector<uint32_t> map[NGROUP];   // item -> job
+  size_t off_map[NGROUP];              // byte offsets in the blob
+  size_t table_bytes;                  // jobs + maps
+  size_t ws_off, ws_bytes;             // b's column outputs
+  int kind;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
+  if (!jobs || njobs == 0) return set_error(PM_EINVAL, "empty job list");
+  if (njobs > (1u << 24)) return set_error(PM_EINVAL, "too many jobs");
+  L->jobs.assign(njobs, JobDev{});
+  for (auto& m : L->map) m.clear();
+  L->kind = KIND_WIDE;
+  size_t ws = 0;
+  std::vector<size_t> ws_job(njobs, 0);
+  for (size_t j = 0; j < njobs; ++j) {
+    const pm_job& in = jobs[j];
+    const std::string tag = "job " + std::to_string(j) + ": ";
+    if (in.log2n < 1 || in.log2n > PM_MAX_LOG2N) return set_error(PM_EINVAL, tag + "log2n must be in [1, 17]");
+    if (in.count == 0) return set_error(PM_EINVAL, tag + "count must be positive");
+    const uint64_t N = 1ull << in.log2n;
+    if (!(in.q & 1) || in.q < 3 || (in.q >> 62)) return set_error(PM_EINVAL, tag + "q must be odd, 3 <= q < 2^62");
+    if ((in.q - 1) % (2 * N)) return set_error(PM_EINVAL, tag + "2N must divide q - 1");
+    const void* ptrs[5] = {in.psi_br, in.psi_inv_br, in.a, in.b, in.c};
+    for (const void* p : ptrs)
+      if (!p || ((uintptr_t)p & 7)) return set_error(PM_EINVAL, tag + "null or misaligned pointer");
+    JobDev& J = L->jobs[j];
+    make_mod(in.q, &J.mod);
+    if (mod_kind(J.mod) != KIND_WIDE) L->kind = KIND_ANY;
+    PassPlan p = plan_for(OP_POLYMUL, in.log2n);
+    J.log2n = in.log2n;
+    J.count = in.count;
+    J.logc = p.logc;
+    J.logr = p.logr;
+    // The product is commutative: when c aliases b, swap so that c can only alias a.
+    const bool swap = (in.c == in.b && in.c != in.a);
+    J.a = swap ? in.b : in.a;
+    J.b = swap ? in.a : in.b;
+    J.c = in.c;
+    J.tf = in.psi_br;
+    J.ti = in.psi_inv_br;
+    J.nops = (J.a == J.b) ? 1 : 2;
+    if (p.R > 1 && J.nops == 2) {
+      ws_job[j] = ws;
+      ws += (size_t)N * in.count * sizeof(uint64_t);
+    }
+  }
+  // work items, in job order within each pass
+  for (size_t j = 0; j < njobs; ++j) {
+    JobDev& J = L->jobs[j];
+    const uint32_t R = 1u << J.logr;
+    auto add = [&](int g, uint64_t n) -> bool {
+      if (L->map[g].size() + n > 0x7fffffffull) return false;
+      J.first[g == G_COLF ? PH_COLF : (g == G_COLI ? PH_COLI : PH_ROW)] = (uint32_t)L->map[g].size();
+      L->map[g].insert(L->map[g].end(), n, (uint32_t)j);
+      return true;
+    };
+    bool ok = true;
+    if (R > 1) {
+      const uint64_t cbs = 1ull << (J.logc - 8);
+      ok = ok && add(G_COLF, (uint64_t)J.nops * J.count * cbs) && add(G_COLI, (uint64_t)J.count * cbs);
+    }
+    const int g = J.logc <= 12 ? G_ROW12 : (J.logc == 13 ? G_ROW13 : G_ROW14);
+    const uint64_t rows_per_item = J.logc <= 12 ? (4096u >> J.logc) : 1;   // RowGeom<logc>::ROWS
+    const uint64_t tasks = (uint64_t)J.count * R;
+    ok = ok && add(g, (tasks + rows_per_item - 1) / rows_per_item);
+    if (!ok) return set_error(PM_EINVAL, "batch has more than 2^31 work items in one pass");
+  }
+  size_t off = align_up(njobs * sizeof(JobDev), 256);
+  for (int g = 0; g < NGROUP; ++g) {
+    L->off_map[g] = off;
+    off = align_up(off + L->map[g].size() * sizeof(uint32_t), 256);
+  }
+  L->table_bytes = off;
+  L->ws_off = off;
+  L->ws_bytes = ws;
+  // remember where each job's b column output goes (relative offsets for now)
+  for (size_t j = 0; j < njobs; ++j) L->jobs[j].wb = (uint64_t*)(uintptr_t)ws_job[j];
+  return PM_OK;
+}
+
+// Writes the table part of the blob for a device base address.
+void fill_blob(const Layout& L, char* host, char* dev_base) {
+  std::vector<JobDev> jd = L.jobs;
+  for (JobDev& J : jd) {
+    if (J.logr > 0) J.wb = J.nops == 2 ? (uint64_t*)(dev_base + L.ws_off + (uintptr_t)J.wb) : J.c;
+    else J.wb = nullptr;
+  }
+  std::memset(host, 0, L.table_bytes);
+  std::memcpy(host, jd.data(), jd.size() * sizeof(JobDev));
+  for (int g = 0; g < NGROUP; ++g)
+    if (!L.map[g].empty()) std::memcpy(host + L.off_map[g], L.map[g].data(), L.map[g].size() * sizeof(uint32_t));
+}
+
+hipError_t launch_all(const Layout& L, char* dev_base, hipStream_t s, bool timed) {
+  const JobDev* jobs = (const JobDev*)dev_base;
+  auto map = [&](int g) { return (const uint32_t*)(dev_base + L.off_map[g]); };
+  struct Step { int group, phase, maxlogc; const char* name; };
+  static const Step steps[NGROUP] = {{G_COLF, PH_COLF, 0, "jobs_col_fwd"}, {G_ROW12, PH_ROW, 12, "jobs_row_mul_c12"},
+                                     {G_ROW13, PH_ROW, 13, "jobs_row_mul_c13"}, {G_ROW14, PH_ROW, 14, "jobs_row_mul_c14"},
+                                     {G_COLI, PH_COLI, 0, "jobs_col_inv"}};
+  for (const Step& st : steps) {
+    const uint32_t n = (uint32_t)L.map[st.group].size();
+    if (n == 0) continue;
+    hipError_t e;
+    if (timed) {
+      ProfScope ps(s, st.name);
+      e = launch_jobs(st.phase, st.maxlogc, L.kind, jobs, map(st.group), n, s);
+    } else {
+      e = launch_jobs(st.phase, st.maxlogc, L.kind, jobs, map(st.group), n, s);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Pinned staging buffers for pm_polymul_jobs: a small ring, each slot reused
+// only after the copy that last read it has completed.
+struct Stage {
+  char* buf = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+std::mutex g_stage_mu;
+Stage g_stage[4];
+unsigned g_stage_next = 0;
+
+}  // namespace
+
+struct pm_plan {
+  int device;
+  Layout L;
+  char* dev = nullptr;
+  size_t dev_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true;
+};
+
+extern "C" {
+
+size_t pm_polymul_jobs_workspace_bytes(const pm_job* jobs, size_t njobs) {
+  Layout L;
+  if (build_layout(jobs, njobs, &L) != PM_OK) return 0;
+  return L.ws_off + L.ws_bytes;
+}
+
+int pm_polymul_jobs(const pm_job* jobs, size_t njobs, void* workspace, size_t workspace_bytes, pm_stream_t stream) {
+  Layout L;
+  int rc = build_layout(jobs, njobs, &L);
+  if (rc) return rc;
+  const size_t need = L.ws_off + L.ws_bytes;
+  if (!workspace || ((uintptr_t)workspace & 255))
+    return set_error(PM_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  if (workspace_bytes < need)
+    return set_error(PM_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)workspace;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    Stage& st = g_stage[g_stage_next++ % 4];
+    if (st.used && hipEventSynchronize(st.done) != hipSuccess) return set_error(PM_EHIP, "staging wait failed");
+    if (st.cap < L.table_bytes) {
+      if (st.buf) (void)hipHostFree(st.buf);
+      st.buf = nullptr;
+      st.cap = 0;
+      if (hipHostMalloc((void**)&st.buf, L.table_bytes, hipHostMallocDefault) != hipSuccess)
+        return set_error(PM_ENOMEM, "pinned staging allocation failed");
+      st.cap = L.table_bytes;
+    }
+    if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess)
+      return set_error(PM_EHIP, "event creation failed");
+    fill_blob(L, st.buf, base);
+    hipError_t e = hipMemcpyAsync(base, st.buf, L.table_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(st.done, s);
+    if (e != hipSuccess) return set_error(PM_EHIP, std::string("job table upload: ") + hipGetErrorString(e));
+    st.used = true;
+  }
+  hipError_t e = launch_all(L, base, s, true);
+  if (e != hipSuccess) return set_error(PM_EHIP, std::string("job launch: ") + hipGetErrorString(e));
+  return set_error(PM_OK, "");
+}
+
+int pm_plan_create(pm_plan** out, const pm_job* jobs, size_t njobs, unsigned flags) {
+  if (!out) return set_error(PM_EINVAL, "plan pointer is null");
+  *out = nullptr;
+  pm_plan* p = new (std::nothrow) pm_plan();
+  if (!p) return set_error(PM_ENOMEM, "host allocation failed");
+  int rc = build_layout(jobs, njobs, &p->L);
+  if (rc) { delete p; return rc; }
+  p->use_graph = !(flags & PM_PLAN_NO_GRAPH);
+  (void)hipGetDevice(&p->device);
+  p->dev_bytes = p->L.ws_off + p->L.ws_bytes;
+  if (hipMalloc((void**)&p->dev, p->dev_bytes) != hipSuccess) {
+    delete p;
+    return set_error(PM_ENOMEM, "device allocation of " + std::to_string(p->dev_bytes) + " bytes failed");
+  }
+  std::vector<char> host(p->L.table_bytes);
+  fill_blob(p->L, host.data(), p->dev);
+  hipError_t e = hipMemcpy(p->dev, host.data(), p->L.table_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess && p->use_graph) {
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t le = launch_all(p->L, p->dev, cs, false);
+      e = hipStreamEndCapture(cs, &p->graph);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  if (e != hipSuccess) {
+    std::string msg = std::string("plan setup: ") + hipGetErrorString(e);
+    pm_plan_destroy(p);
+    return set_error(PM_EHIP, msg);
+  }
+  *out = p;
+  return set_error(PM_OK, "");
+}
+
+int pm_plan_launch(pm_plan* p, pm_stream_t stream) {
+  if (!p) return set_error(PM_EINVAL, "plan is null");
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  if (dev != p->device) return set_error(PM_EINVAL, "plan belongs to another device");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (p->use_graph) {
+    ProfScope ps(s, "plan_graph");
+    e = hipGraphLaunch(p->exec, s);
+  } else {
+    e = launch_all(p->L, p->dev, s, true);
+  }
+  if (e != hipSuccess) return set_error(PM_EHIP, std::string("plan launch: ") + hipGetErrorString(e));
+  return set_error(PM_OK, "");
+}
+
+int pm_plan_destroy(pm_plan* p) {
+  if (!p) return PM_OK;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->dev) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->dev);
+  }
+  delete p;
+  return PM_OK;
+}
+
+size_t pm_plan_device_bytes(const pm_plan* p) { return p ? p->dev_bytes : 0; }
+
+}  // extern "C"

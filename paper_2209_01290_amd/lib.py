@@ -31,6 +31,13 @@ class ProfEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
+class Job(ctypes.Structure):
+    """pm_job: `count` pairs sharing N = 2^log2n and q (device pointers)."""
+    _fields_ = [("log2n", ctypes.c_uint32), ("count", ctypes.c_uint32), ("q", ctypes.c_uint64),
+                ("psi_br", ctypes.c_void_p), ("psi_inv_br", ctypes.c_void_p),
+                ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("c", ctypes.c_void_p)]
+
+
 class PMError(RuntimeError):
     def __init__(self, code: int, func: str, msg: str):
         super().__init__("%s failed (%d): %s" % (func, code, msg))
@@ -64,6 +71,12 @@ def load():
             "pm_find_psi": (u64, [u64, sz]),
             "pm_make_tables": (i32, [u64, sz, u64, u64p, u64p]),
             "pm_prof_enable": (i32, [i32]),
+            "pm_polymul_jobs_workspace_bytes": (sz, [ctypes.POINTER(Job), sz]),
+            "pm_polymul_jobs": (i32, [ctypes.POINTER(Job), sz, vp, sz, vp]),
+            "pm_plan_create": (i32, [ctypes.POINTER(vp), ctypes.POINTER(Job), sz, ctypes.c_uint]),
+            "pm_plan_launch": (i32, [vp, vp]),
+            "pm_plan_destroy": (i32, [vp]),
+            "pm_plan_device_bytes": (sz, [vp]),
             "pm_prof_read": (i32, [ctypes.POINTER(ProfEntry), sz, ctypes.POINTER(sz), i32]),
         }
         for name, (res, args) in sig.items():
@@ -79,7 +92,9 @@ def exported_symbols():
     return ["pm_last_error", "pm_barrett_mulmod", "pm_ntt_fwd", "pm_ntt_inv", "pm_polymul",
             "pm_polymul_workspace_bytes", "pm_polymul_stagewise",
             "pm_polymul_stagewise_workspace_bytes", "pm_tune_set", "pm_tune_get",
-            "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read"]
+            "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read",
+            "pm_polymul_jobs_workspace_bytes", "pm_polymul_jobs", "pm_plan_create", "pm_plan_launch",
+            "pm_plan_destroy", "pm_plan_device_bytes"]
 
 
 def _check(rc: int, func: str):
@@ -158,6 +173,52 @@ def pm_polymul_stagewise(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_b
                                        polys_per_limb, _qarr(q, limbs), _dptr(psi_br, "psi_br"),
                                        _dptr(psi_inv_br, "psi_inv_br"), _dptr(workspace, "workspace"),
                                        _stream(stream, a)), "pm_polymul_stagewise")
+
+
+PM_PLAN_NO_GRAPH = 1
+
+
+def make_job(log2n, count, q, psi_br, psi_inv_br, a, b, c):
+    """A pm_job from tensors (device pointers are taken, the tensors must outlive its use)."""
+    return Job(log2n, count, int(q), _dptr(psi_br, "psi_br"), _dptr(psi_inv_br, "psi_inv_br"),
+               _dptr(a, "a"), _dptr(b, "b"), _dptr(c, "c"))
+
+
+def _jobarr(jobs):
+    arr = (Job * len(jobs))(*jobs)
+    return arr, len(jobs)
+
+
+def pm_polymul_jobs_workspace_bytes(jobs):
+    arr, n = _jobarr(jobs)
+    return int(load().pm_polymul_jobs_workspace_bytes(arr, n))
+
+
+def pm_polymul_jobs(jobs, workspace, stream=None):
+    arr, n = _jobarr(jobs)
+    _check(load().pm_polymul_jobs(arr, n, _dptr(workspace, "workspace"),
+                                  workspace.numel() * workspace.element_size(), _stream(stream, workspace)),
+           "pm_polymul_jobs")
+
+
+def pm_plan_create(jobs, flags=0):
+    """Returns an opaque plan handle (int); free it with pm_plan_destroy."""
+    arr, n = _jobarr(jobs)
+    h = ctypes.c_void_p()
+    _check(load().pm_plan_create(ctypes.byref(h), arr, n, flags), "pm_plan_create")
+    return h.value
+
+
+def pm_plan_launch(plan, stream=None):
+    _check(load().pm_plan_launch(plan, _stream(stream)), "pm_plan_launch")
+
+
+def pm_plan_destroy(plan):
+    _check(load().pm_plan_destroy(plan), "pm_plan_destroy")
+
+
+def pm_plan_device_bytes(plan):
+    return int(load().pm_plan_device_bytes(plan))
 
 
 def pm_tune_set(op, log2n, logc):

@@ -1,0 +1,135 @@
+"""Batched job tables (pm_polymul_jobs, pm_plan_*): mixed N, moduli and
+aliasing in one batch, checked word for word against the oracle; graph
+replays checked one by one with eager work in between."""
+import numpy as np
+import pytest
+
+from gpu_helpers import first_mismatch, oracle_polymul, oracle_tables
+from paper_2209_01290_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2209_01290_amd import lib
+    lib.load()
+    return lib
+
+
+# (log2n, count, bits of the prime search, prime index, alias)
+MIX = [(1, 3, 60, 0, ""), (4, 2, 60, 1, "c=a"), (8, 5, 30, 0, ""), (10, 4, 60, 2, "c=b"),
+       (12, 3, 60, 0, ""), (13, 2, 62, 0, "a=b"), (14, 2, 60, 3, ""), (15, 1, 61, 0, "c=a"),
+       (16, 3, 60, 1, "c=b"), (17, 2, 60, 0, ""), (16, 1, 35, 0, "a=b=c"), (11, 7, 60, 4, "")]
+
+
+def _build(L, mix, request0=0):
+    import torch
+    jobs, keep, want = [], [], []
+    for i, (log2n, count, bits, qi, alias) in enumerate(mix):
+        N = 1 << log2n
+        q = L.pm_ntt_primes(N, qi + 1, bits)[qi]
+        a, b = synth.operands(synth.SEED_BASE + 4, [q], count, N, request=request0 + i)
+        if "a=b" in alias:
+            b = a.copy()
+        fw_o, iv_o = oracle_tables([q], N)
+        want.append(oracle_polymul(a, b, [q], N, fw_o, iv_o)[0])
+        fw, iv = L.pm_make_tables(q, N)
+        dfw, div = L.to_device(fw), L.to_device(iv)
+        da = L.to_device(a[0])
+        db = da if "a=b" in alias else L.to_device(b[0])
+        if alias == "c=a" or alias == "a=b=c":
+            dc = da
+        elif alias == "c=b":
+            dc = db
+        else:
+            dc = torch.empty_like(da)
+        jobs.append(L.make_job(log2n, count, q, dfw, div, da, db, dc))
+        keep.append((dfw, div, da, db, dc, a, b))
+    return jobs, keep, want
+
+
+def _check_all(L, keep, want, what):
+    for i, (k, w) in enumerate(zip(keep, want)):
+        got = L.to_host(k[4]).reshape(w.shape)
+        msg = first_mismatch(got, w)
+        assert msg is None, "%s job %d (N=2^%d): %s" % (what, i, MIX[i][0] if i < len(MIX) else -1, msg)
+
+
+def test_jobs_one_shot(L):
+    import torch
+    jobs, keep, want = _build(L, MIX)
+    nbytes = L.pm_polymul_jobs_workspace_bytes(jobs)
+    assert nbytes > 0
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device="cuda")
+    L.pm_polymul_jobs(jobs, ws)
+    torch.cuda.synchronize()
+    _check_all(L, keep, want, "one-shot")
+
+
+@pytest.mark.parametrize("flags", [0, 1], ids=["graph", "direct"])
+def test_plan_replays(L, flags):
+    """A plan replayed several times, with eager library work and host
+    synchronization between replays; every replay is checked."""
+    import torch
+    jobs, keep, want = _build(L, MIX, request0=50)
+    plan = L.pm_plan_create(jobs, flags)
+    try:
+        assert L.pm_plan_device_bytes(plan) > 0
+        for rep in range(3):
+            # restore the inputs that the previous replay overwrote (aliased outputs)
+            for k in keep:
+                k[2].copy_(L.to_device(k[5][0]))
+                if k[3].data_ptr() != k[2].data_ptr():
+                    k[3].copy_(L.to_device(k[6][0]))
+            # unrelated eager work on the same stream between replays
+            x = L.to_device(np.arange(1, 1025, dtype=np.uint64))
+            L.pm_barrett_mulmod(x, x, x, 12289)
+            torch.cuda.synchronize()
+            L.pm_plan_launch(plan)
+            torch.cuda.synchronize()
+            _check_all(L, keep, want, "replay %d" % rep)
+    finally:
+        L.pm_plan_destroy(plan)
+
+
+def test_plan_reads_new_inputs(L):
+    """Buffers are read again at each launch: new operands give new products."""
+    import torch
+    mix = [(16, 2, 60, 0, ""), (12, 3, 60, 1, "")]
+    jobs, keep, want = _build(L, mix, request0=90)
+    plan = L.pm_plan_create(jobs)
+    try:
+        L.pm_plan_launch(plan)
+        torch.cuda.synchronize()
+        for k, w in zip(keep, want):
+            assert first_mismatch(L.to_host(k[4]).reshape(w.shape), w) is None
+        # new operands in the same buffers
+        for i, (log2n, count, bits, qi, _) in enumerate(mix):
+            N = 1 << log2n
+            q = L.pm_ntt_primes(N, qi + 1, bits)[qi]
+            a, b = synth.operands(synth.SEED_BASE + 5, [q], count, N, request=i)
+            keep[i][2].copy_(L.to_device(a[0]))
+            keep[i][3].copy_(L.to_device(b[0]))
+            fw_o, iv_o = oracle_tables([q], N)
+            want[i] = oracle_polymul(a, b, [q], N, fw_o, iv_o)[0]
+        L.pm_plan_launch(plan)
+        torch.cuda.synchronize()
+        for k, w in zip(keep, want):
+            assert first_mismatch(L.to_host(k[4]).reshape(w.shape), w) is None
+    finally:
+        L.pm_plan_destroy(plan)
+
+
+def test_jobs_validation(L):
+    import torch
+    jobs, keep, _ = _build(L, [(10, 1, 60, 0, "")])
+    bad = L.Job.from_buffer_copy(jobs[0])
+    bad.q = bad.q + 2
+    with pytest.raises(L.PMError):
+        L.pm_plan_create([bad])
+    ws = torch.empty(16, dtype=torch.int64, device="cuda")
+    with pytest.raises(L.PMError):
+        L.pm_polymul_jobs(jobs + [bad], ws)
