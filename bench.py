@@ -145,6 +145,58 @@ def cpu_baseline(N, qs, a_host, b_host, gpu_c, budget_s=12.0):
                       % (threads * reps, reps, threads, sorted(set(l for l, _ in pairs)), 1e3 * t1)}
 
 
+def mixed_batch(torch, lib, dev, launches=5):
+    """The batched mixed workload: 512 requests, N uniform on 2^12..2^17, 1..48
+    limbs, all in one plan (one graph launch), against one pm_polymul call
+    per request (same kernels, batched across limbs only)."""
+    from paper_2209_01290_amd import workloads
+    reqs = workloads.mixed_requests(220901290 + 4)
+    mb = workloads.MixedBatch(reqs, 220901290 + 4, dev)
+    work16 = sum((1 << n) * n for n, L in reqs for _ in range(L)) / float((1 << 16) * 16)
+    plan = lib.pm_plan_create(mb.jobs)
+    stream = torch.cuda.current_stream(dev)
+    try:
+        for _ in range(2):
+            lib.pm_plan_launch(plan)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(launches):
+            lib.pm_plan_launch(plan)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        per = [ev[k].elapsed_time(ev[k + 1]) for k in range(launches)]
+        dev_bytes = lib.pm_plan_device_bytes(plan)
+    finally:
+        lib.pm_plan_destroy(plan)
+    ms = sum(per) / len(per)
+    maxws = max(lib.pm_polymul_workspace_bytes(1 << n, L, 1) for n, L in reqs)
+    ws = torch.empty(max(maxws // 8, 1), dtype=torch.int64, device=dev)
+
+    def per_request():
+        for r, (n, L) in enumerate(reqs):
+            prm = mb.tables.get(n, 0)
+            a, b, c = mb.request_limbs(r)
+            lib.pm_polymul(a, b, c, 1 << n, L, 1, prm.q[:L], prm.psi_br[:L], prm.psi_inv_br[:L], ws)
+
+    per_request()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    per_request()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1)
+    return {"what": "512 requests, N uniform on 2^12..2^17, 1..48 limbs (%d limb-products), one plan "
+                    "(HIP graph) launch per batch" % mb.products,
+            "products": mb.products, "ms_per_batch": round(ms, 3), "p99_ms": round(pct(per, 99), 3),
+            "value": round(mb.products / ms * 1e3, 1), "unit": "polymul/s",
+            "n16_equivalent_per_s": round(work16 / ms * 1e3, 1),
+            "plan_device_bytes": dev_bytes,
+            "per_request_ms": round(ms_plain, 3),
+            "per_request_value": round(mb.products / ms_plain * 1e3, 1),
+            "batched_over_per_request": round(ms_plain / ms, 3)}
+
+
 def copy_probe(torch, dev, steps):
     """Plain device-to-device copies of 1 GiB: a kernel of known HBM traffic
     (1 GiB read + 1 GiB written per launch) for scaling rocprofv3 counters."""
@@ -309,6 +361,7 @@ def main():
         # restore the batched result for the CPU check below
         step()
         torch.cuda.synchronize()
+        out["mixed_batch"] = mixed_batch(torch, lib, dev)
 
     if not args.no_cpu:
         gpu_c = lib.to_host(dc).reshape(a_host.shape)

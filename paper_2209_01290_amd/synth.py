@@ -92,3 +92,56 @@ def operands(seed: int, q_per_limb, polys: int, N: int, request: int = 0):
             a[l, p] = uniform_mod(key(seed, request, l, p, 0), N, int(q))
             b[l, p] = uniform_mod(key(seed, request, l, p, 1), N, int(q))
     return a, b
+
+
+# ------------------------------------------------------------ on the device --
+# The same generator on a HIP device with torch int64 tensors (two's-complement
+# wrap-around; logical right shifts are arithmetic shifts masked to the low
+# 64-k bits), for workloads too large to draw on the host. Bit-identical to
+# uniform_mod (tested).
+
+def _s64(x: int) -> int:
+    x &= _M64
+    return x - (1 << 64) if x >> 63 else x
+
+
+def _lsr(z, k):
+    import torch
+    if isinstance(k, int):
+        return torch.bitwise_and(torch.bitwise_right_shift(z, k), (1 << (64 - k)) - 1)
+    mask = torch.bitwise_left_shift(torch.ones_like(k), 64 - k) - 1   # k >= 2 here
+    return torch.bitwise_and(torch.bitwise_right_shift(z, k), mask)
+
+
+def _mix_t(z):
+    z = z ^ _lsr(z, 30)
+    z = z * _s64(0xBF58476D1CE4E5B9)
+    z = z ^ _lsr(z, 27)
+    z = z * _s64(0x94D049BB133111EB)
+    return z ^ _lsr(z, 31)
+
+
+def uniform_mod_device(keys, n, qs, out):
+    """out[s, :n] = uniform_mod(keys[s], n, qs[s]) for every stream s, drawn on
+    out's device. out: int64 tensor [S, n]."""
+    import torch
+    dev = out.device
+    S = len(keys)
+    assert out.shape[0] == S and out.shape[1] == n
+    j = torch.arange(1, n + 1, dtype=torch.int64, device=dev).unsqueeze(0)
+    g = _s64(0x9E3779B97F4A7C15)
+    kt = torch.tensor([_s64(k) for k in keys], dtype=torch.int64, device=dev).unsqueeze(1)
+    qt = torch.tensor([int(q) for q in qs], dtype=torch.int64, device=dev).unsqueeze(1)
+    sh = torch.tensor([64 - int(q).bit_length() for q in qs], dtype=torch.int64, device=dev).unsqueeze(1)
+    v = _lsr(_mix_t(kt + g * j), sh)
+    attempt = 1
+    bad = v >= qt
+    while bool(bad.any()):
+        k2 = torch.tensor([_s64(_mix_int(int(k) ^ attempt)) for k in keys], dtype=torch.int64,
+                          device=dev).unsqueeze(1)
+        v2 = _lsr(_mix_t(k2 + g * j), sh)
+        v = torch.where(bad, v2, v)
+        bad = bad & (v2 >= qt)
+        attempt += 1
+    out.copy_(v)
+    return out
