@@ -237,6 +237,7 @@ def main():
     from paper_2209_01290_amd import lib, synth
 
     lib.load()
+    tuned = lib.apply_tune_db()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.copy_probe:
@@ -303,7 +304,8 @@ def main():
         "config": {"workload": "N=2^16 negacyclic polymul, 48 limbs x 8 pairs (384 products), "
                                "48 largest 60-bit primes q = 1 mod 2^17, uniform operands",
                    "N": N, "limbs": LIMBS, "polys_per_limb": POLYS, "path": "pm_polymul (batched)",
-                   "pass_plan_logc": lib.pm_tune_get(lib.OP_POLYMUL, N_LOG2)},
+                   "pass_plan_logc": lib.pm_tune_get(lib.OP_POLYMUL, N_LOG2),
+                   "tuned_entries": tuned},
         "latency_ms": {"p50": round(pct(step_ms, 50), 4), "p99": round(pct(step_ms, 99), 4),
                        "unit": "per batched step of 384 products"},
         "roofline": roofline,

@@ -232,6 +232,25 @@ def pm_tune_get(op, log2n):
     return r
 
 
+def apply_tune_db(path=None):
+    """Install the pass plans of an autotuner database (see tune.py); returns
+    the number of entries applied, 0 if the file does not exist."""
+    import json
+    if path is None:
+        path = os.path.join(PKG, "tune_db", "gfx950.json")
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        db = json.load(f)
+    ops = {"polymul": OP_POLYMUL, "ntt_fwd": OP_NTT_FWD, "ntt_inv": OP_NTT_INV}
+    n = 0
+    for name, table in db.get("choices", {}).items():
+        for log2n, logc in table.items():
+            pm_tune_set(ops[name], int(log2n), int(logc))
+            n += 1
+    return n
+
+
 def pm_prof_enable(on=True):
     _check(load().pm_prof_enable(1 if on else 0), "pm_prof_enable")
 

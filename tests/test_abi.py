@@ -101,3 +101,24 @@ def test_host_params_match_oracle(L, N, count):
             f, i = L.pm_make_tables(q, N)
             f2, i2 = o.psi_tables(q, N)
             assert np.array_equal(f, f2) and np.array_equal(i, i2)
+
+
+def test_tune_db_applies(L, tmp_path):
+    import json
+    from paper_2209_01290_amd import tune
+    assert tune.candidates(16) == [11, 12, 13, 14] and tune.candidates(8) == [8]
+    db = {"choices": {"polymul": {"15": 11}, "ntt_fwd": {"13": 8}}}
+    p = tmp_path / "db.json"
+    p.write_text(json.dumps(db))
+    try:
+        assert L.apply_tune_db(str(p)) == 2
+        assert L.pm_tune_get(L.OP_POLYMUL, 15) == 11 and L.pm_tune_get(L.OP_NTT_FWD, 13) == 8
+        assert L.apply_tune_db(str(tmp_path / "missing.json")) == 0
+        # the packaged database only names implemented splits
+        shipped = json.load(open(tune.DEFAULT_DB))
+        for name, table in shipped["choices"].items():
+            for log2n, logc in table.items():
+                assert logc in tune.candidates(int(log2n))
+    finally:
+        L.pm_tune_set(L.OP_POLYMUL, 15, 0)
+        L.pm_tune_set(L.OP_NTT_FWD, 13, 0)
