@@ -197,6 +197,16 @@ def mixed_batch(torch, lib, dev, launches=5):
             "batched_over_per_request": round(ms_plain / ms, 3)}
 
 
+def serving(lib, rates=(5000.0, 20000.0, 50000.0), nreq=4000):
+    """The continuous-batching loop on Poisson arrivals (N in 2^13..2^17,
+    1..60 limbs): throughput and p50/p99 latency per offered rate."""
+    from paper_2209_01290_amd import serve
+    res = serve.run_rates(rates, nreq, budget_gib=32.0, streams=3, verbose=False)
+    keep = ("offered_rate_req_s", "completed", "throughput_req_s", "throughput_polymul_s",
+            "throughput_n16_equiv_s", "latency_ms", "mean_batch_requests", "max_queue")
+    return [{k: r[k] for k in keep} for r in res]
+
+
 def copy_probe(torch, dev, steps):
     """Plain device-to-device copies of 1 GiB: a kernel of known HBM traffic
     (1 GiB read + 1 GiB written per launch) for scaling rocprofv3 counters."""
@@ -364,6 +374,7 @@ def main():
         step()
         torch.cuda.synchronize()
         out["mixed_batch"] = mixed_batch(torch, lib, dev)
+        out["serving"] = serving(lib)
 
     if not args.no_cpu:
         gpu_c = lib.to_host(dc).reshape(a_host.shape)

@@ -201,6 +201,18 @@ def pm_polymul_jobs(jobs, workspace, stream=None):
            "pm_polymul_jobs")
 
 
+def pm_polymul_jobs_workspace_bytes_raw(jobs_ptr, njobs):
+    """As pm_polymul_jobs_workspace_bytes, for a host array of pm_job records at jobs_ptr."""
+    return int(load().pm_polymul_jobs_workspace_bytes(ctypes.cast(jobs_ptr, ctypes.POINTER(Job)), njobs))
+
+
+def pm_polymul_jobs_raw(jobs_ptr, njobs, workspace_ptr, workspace_bytes, stream):
+    """As pm_polymul_jobs, for a host array of pm_job records at jobs_ptr and raw
+    device / stream handles."""
+    _check(load().pm_polymul_jobs(ctypes.cast(jobs_ptr, ctypes.POINTER(Job)), njobs, workspace_ptr,
+                                  workspace_bytes, stream), "pm_polymul_jobs")
+
+
 def pm_plan_create(jobs, flags=0):
     """Returns an opaque plan handle (int); free it with pm_plan_destroy."""
     arr, n = _jobarr(jobs)

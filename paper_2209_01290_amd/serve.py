@@ -1,0 +1,339 @@
+"""Continuous-batching request loop for negacyclic products.
+
+A request is an RNS product: L limbs of size N (limb l modulo the l-th
+largest 60-bit prime q = 1 mod 2N), i.e. L jobs of one pair each. Requests
+arrive on a clock (a seeded Poisson trace); the loop
+
+  * queues arrivals in FIFO order;
+  * admits the head of the queue while its HBM footprint (output words plus
+    the column-pass intermediate) fits the free part of a device arena, so
+    requests that arrive while others run are admitted as memory frees up;
+  * forms a batch of every newly admitted request -- any mix of N -- and
+    launches it as one pm_polymul_jobs call (one launch per pass for the
+    whole mix) on the next of S streams, so up to S batches overlap on the
+    device;
+  * polls the batches' completion events, records each request's latency
+    (completion seen on the host minus arrival) and frees its memory.
+
+Operands stay resident on the device: per N, a pool of operand sets (60 limbs
+each) drawn once with the device generator; request r uses pool entry
+r mod pool_size. Twiddle tables for every (N, limb) are resident as well.
+
+The scheduling logic is independent of the device: `Engine` drives an
+executor object; `GpuExecutor` runs the library, tests on the CPU use a fake.
+
+Usage:  python -m paper_2209_01290_amd.serve --rates 2000,5000,10000,20000,50000
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import time
+
+import numpy as np
+
+from . import workloads
+
+SEED = 220901290 + 5
+ALIGN = 256
+
+# pm_job as a numpy record (layout of include/pm.h: two uint32, one uint64, five pointers)
+JOB_DTYPE = np.dtype([("log2n", "<u4"), ("count", "<u4"), ("q", "<u8"), ("psi_br", "<u8"),
+                      ("psi_inv_br", "<u8"), ("a", "<u8"), ("b", "<u8"), ("c", "<u8")])
+
+
+class Arena:
+    """First-fit allocator of byte ranges of one device buffer (host-side book-keeping)."""
+
+    def __init__(self, size: int):
+        self.size = size
+        self.free = [(0, size)]          # sorted (offset, length)
+        self.used = 0
+        self.peak = 0
+
+    def alloc(self, n: int):
+        n = (n + ALIGN - 1) // ALIGN * ALIGN
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + n, ln - n)
+                self.used += n
+                self.peak = max(self.peak, self.used)
+                return off, n
+        return None
+
+    def release(self, off: int, n: int):
+        self.used -= n
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        self.free.insert(i, (off, n))
+        # coalesce with neighbours
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:
+            self.free[i] = (off, n + self.free[i + 1][1])
+            self.free.pop(i + 1)
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            self.free.pop(i)
+
+
+class Request:
+    __slots__ = ("rid", "arrival", "log2n", "limbs", "t_admit", "t_done", "alloc", "state")
+
+    def __init__(self, rid, arrival, log2n, limbs):
+        self.rid, self.arrival, self.log2n, self.limbs = rid, arrival, log2n, limbs
+        self.t_admit = self.t_done = None
+        self.alloc = None
+        self.state = "pending"
+
+
+def footprint(log2n: int, limbs: int) -> int:
+    """Arena bytes a request holds while admitted: its output words."""
+    return (1 << log2n) * limbs * 8
+
+
+def batch_workspace(log2n: int, limbs: int) -> int:
+    """Upper bound of the workspace bytes a request adds to its batch: the
+    column-pass copy of b when the product runs in two passes, plus its
+    job-table entries (one 120-byte record and at most 80 work-item slots of
+    4 bytes per limb). A batch also needs BATCH_WS_SLACK for alignment."""
+    N = 1 << log2n
+    return (N * limbs * 8 if log2n > 12 else 0) + limbs * 512
+
+
+BATCH_WS_SLACK = 8192
+
+
+class Engine:
+    def __init__(self, executor, budget_bytes: int, streams: int = 3, max_batch_products: int = 4096,
+                 batch_ws_bytes: int | None = None):
+        self.ex = executor
+        self.arena = Arena(budget_bytes)
+        self.streams = streams
+        self.max_batch_products = max_batch_products
+        self.batch_ws = batch_ws_bytes if batch_ws_bytes is not None else executor.batch_workspace_bytes()
+
+    def run(self, trace, time_scale: float = 1.0, on_complete=None):
+        """trace: [(arrival_s, log2n, limbs)] sorted by arrival. Returns stats."""
+        reqs = [Request(i, t * time_scale, n, L) for i, (t, n, L) in enumerate(trace)]
+        queue = collections.deque()
+        inflight = collections.deque()          # (handle, [requests], unused)
+        max_inflight = 0
+        rejected = []
+        nxt = 0
+        done = 0
+        batches, batch_sizes, max_queue = 0, [], 0
+        t0 = time.monotonic()
+        while done + len(rejected) < len(reqs):
+            now = time.monotonic() - t0
+            while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                r = reqs[nxt]
+                if footprint(r.log2n, r.limbs) > self.arena.size or \
+                        batch_workspace(r.log2n, r.limbs) > self.batch_ws - BATCH_WS_SLACK:
+                    r.state = "rejected"
+                    rejected.append(r)
+                else:
+                    queue.append(r)
+                nxt += 1
+            max_queue = max(max_queue, len(queue))
+            # completions
+            while inflight and self.ex.done(inflight[0][0]):
+                handle, batch, _ = inflight.popleft()
+                tdone = time.monotonic() - t0
+                for r in batch:
+                    r.t_done = tdone
+                    r.state = "done"
+                    if on_complete is not None:
+                        on_complete(r, self.ex)
+                    self.arena.release(*r.alloc)
+                    done += 1
+                self.ex.finish(handle)
+            # admission and launch
+            if queue and len(inflight) < self.streams:
+                batch, products, wsb = [], 0, 0
+                while queue and products + queue[0].limbs <= self.max_batch_products:
+                    r = queue[0]
+                    need = batch_workspace(r.log2n, r.limbs)
+                    if wsb + need > self.batch_ws - BATCH_WS_SLACK:
+                        break
+                    a = self.arena.alloc(footprint(r.log2n, r.limbs))
+                    if a is None:
+                        break
+                    queue.popleft()
+                    r.alloc, r.t_admit, r.state = a, now, "admitted"
+                    batch.append(r)
+                    products += r.limbs
+                    wsb += need
+                if batch:
+                    handle = self.ex.launch(batch, batches)
+                    inflight.append((handle, batch, None))
+                    max_inflight = max(max_inflight, len(inflight))
+                    batches += 1
+                    batch_sizes.append(len(batch))
+                    continue
+            if not inflight and not queue and nxt < len(reqs):
+                dt = reqs[nxt].arrival - (time.monotonic() - t0)
+                if dt > 0:
+                    time.sleep(min(dt, 0.002))
+            elif inflight:
+                time.sleep(0)   # yield; completion is polled
+        wall = time.monotonic() - t0
+        ok = [r for r in reqs if r.state == "done"]
+        lat = np.array([r.t_done - r.arrival for r in ok]) * 1e3
+        n16 = sum(((1 << r.log2n) * r.log2n * r.limbs) for r in ok) / float((1 << 16) * 16)
+        span = (max(r.t_done for r in ok) - min(r.arrival for r in ok)) if ok else 0.0
+        return {
+            "requests": len(reqs), "completed": len(ok), "rejected": len(rejected),
+            "limb_products": int(sum(r.limbs for r in ok)),
+            "wall_s": round(wall, 4),
+            "throughput_req_s": round(len(ok) / span, 1) if span > 0 else None,
+            "throughput_polymul_s": round(sum(r.limbs for r in ok) / span, 1) if span > 0 else None,
+            "throughput_n16_equiv_s": round(n16 / span, 1) if span > 0 else None,
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
+                           "p99": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
+                           "mean": round(float(lat.mean()), 3) if len(lat) else None},
+            "batches": batches, "mean_batch_requests": round(float(np.mean(batch_sizes)), 2) if batch_sizes else 0,
+            "max_queue": max_queue, "max_inflight_batches": max_inflight,
+            "arena_peak_bytes": self.arena.peak, "arena_bytes": self.arena.size,
+            "_requests": reqs,
+        }
+
+
+class GpuExecutor:
+    """Runs batches with pm_polymul_jobs: outputs in a device arena, one fixed
+    workspace per stream, operand pools and tables resident."""
+
+    def __init__(self, budget_bytes: int, streams: int = 3, pool: int = 4, max_limbs: int = 60,
+                 log2ns=workloads.SERVE_LOG2N, device="cuda", seed: int = SEED,
+                 ws_bytes_per_stream: int = 2 << 30):
+        import torch
+        from . import lib, synth
+        self.torch, self.lib = torch, lib
+        lib.load()
+        self.dev = torch.device(device)
+        self.arena_t = torch.empty(budget_bytes // 8, dtype=torch.int64, device=self.dev)
+        self.base = self.arena_t.data_ptr()
+        self.streams = [torch.cuda.Stream(self.dev) for _ in range(streams)]
+        self.ws = [torch.empty(ws_bytes_per_stream // 8, dtype=torch.int64, device=self.dev) for _ in range(streams)]
+        self.ws_bytes = ws_bytes_per_stream
+        self.pool = pool
+        self.max_limbs = max_limbs
+        self.tables = workloads.Tables(self.dev)
+        self.inputs = {}
+        self.seed = seed
+        for log2n in log2ns:
+            N = 1 << log2n
+            prm = self.tables.get(log2n, max_limbs)
+            a = torch.empty((pool, max_limbs, N), dtype=torch.int64, device=self.dev)
+            b = torch.empty_like(a)
+            for p in range(pool):
+                synth.uniform_mod_device([synth.key(seed, p, l, 0, 0) for l in range(max_limbs)], N,
+                                         prm.q[:max_limbs], a[p])
+                synth.uniform_mod_device([synth.key(seed, p, l, 0, 1) for l in range(max_limbs)], N,
+                                         prm.q[:max_limbs], b[p])
+            self.inputs[log2n] = (a, b)
+        torch.cuda.synchronize()
+
+    def budget(self):
+        return self.arena_t.numel() * 8
+
+    def batch_workspace_bytes(self):
+        return self.ws_bytes
+
+    def resident_bytes(self):
+        t = sum(2 * x[0].numel() * 8 for x in self.inputs.values())
+        t += sum(2 * p.psi_br.numel() * 8 for p in self.tables.by_n.values())
+        return t + self.budget() + len(self.ws) * self.ws_bytes
+
+    def job_rows(self, r, out_ptr=None):
+        """pm_job records of request r (output in its arena slot, or at out_ptr)."""
+        N = 1 << r.log2n
+        prm = self.tables.get(r.log2n, 0)
+        a, b = self.inputs[r.log2n]
+        p = r.rid % self.pool
+        L = r.limbs
+        rows = np.zeros(L, dtype=JOB_DTYPE)
+        rows["log2n"] = r.log2n
+        rows["count"] = 1
+        rows["q"] = np.array(prm.q[:L], dtype=np.uint64)
+        lidx = np.arange(L, dtype=np.uint64)
+        step = np.uint64(N * 8)
+        rows["psi_br"] = np.uint64(prm.psi_br.data_ptr()) + lidx * step
+        rows["psi_inv_br"] = np.uint64(prm.psi_inv_br.data_ptr()) + lidx * step
+        rows["a"] = np.uint64(a[p].data_ptr()) + lidx * step
+        rows["b"] = np.uint64(b[p].data_ptr()) + lidx * step
+        base = out_ptr if out_ptr is not None else self.base + r.alloc[0]
+        rows["c"] = np.uint64(base) + lidx * step
+        return rows
+
+    def inputs_of(self, r):
+        a, b = self.inputs[r.log2n]
+        p = r.rid % self.pool
+        return a[p, :r.limbs], b[p, :r.limbs]
+
+    def output(self, r):
+        N = 1 << r.log2n
+        off = r.alloc[0] // 8
+        return self.arena_t[off: off + r.limbs * N].view(r.limbs, N)
+
+    def launch(self, batch, k):
+        jobs = np.concatenate([self.job_rows(r) for r in batch])
+        i = k % len(self.streams)
+        s, ws = self.streams[i], self.ws[i]
+        self.lib.pm_polymul_jobs_raw(jobs.ctypes.data, len(jobs), ws.data_ptr(), self.ws_bytes, s.cuda_stream)
+        ev = self.torch.cuda.Event()
+        ev.record(s)
+        return (ev, s)
+
+    def run_alone(self, r):
+        """Request r on its own (same entry point), into a fresh output tensor."""
+        torch = self.torch
+        out = torch.empty((r.limbs, 1 << r.log2n), dtype=torch.int64, device=self.dev)
+        jobs = self.job_rows(r, out_ptr=out.data_ptr())
+        need = self.lib.pm_polymul_jobs_workspace_bytes_raw(jobs.ctypes.data, len(jobs))
+        ws = torch.empty(max(need // 8 + 64, 64), dtype=torch.int64, device=self.dev)
+        self.lib.pm_polymul_jobs_raw(jobs.ctypes.data, len(jobs), ws.data_ptr(), ws.numel() * 8,
+                                     torch.cuda.current_stream(self.dev).cuda_stream)
+        torch.cuda.synchronize()
+        return out
+
+    def done(self, handle):
+        return handle[0].query()
+
+    def finish(self, handle):
+        pass
+
+
+def run_rates(rates, nreq, budget_gib=32.0, streams=3, seed=SEED, verbose=True, ex=None):
+    ex = ex or GpuExecutor(int(budget_gib * (1 << 30)), streams=streams, seed=seed)
+    out = []
+    for rate in rates:
+        trace = [(t, n, L) for (t, n, L) in workloads.serving_requests(seed + int(rate), nreq, rate)]
+        eng = Engine(ex, ex.budget(), streams=streams)
+        st = eng.run(trace)
+        st.pop("_requests")
+        st["offered_rate_req_s"] = rate
+        out.append(st)
+        if verbose:
+            print(json.dumps(st), flush=True)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--rates", default="2000,5000,10000,20000,50000")
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--budget-gib", type=float, default=32.0)
+    ap.add_argument("--streams", type=int, default=3)
+    a = ap.parse_args()
+    from . import lib
+    lib.load()
+    lib.apply_tune_db()
+    run_rates([float(x) for x in a.rates.split(",")], a.requests, a.budget_gib, a.streams)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,97 @@
+"""The serving loop's scheduling on the CPU, with a fake executor whose
+batches complete after a modelled time: every request completes once, FIFO
+admission, the arena never overflows, batches overlap (continuous batching),
+oversize requests are rejected, a tiny budget forces queueing."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2209_01290_amd import serve, workloads
+
+
+class FakeExecutor:
+    def __init__(self, us_per_product=20.0, ws_bytes=1 << 30):
+        self.us = us_per_product
+        self.ws_bytes = ws_bytes
+        self.launched = []
+
+    def batch_workspace_bytes(self):
+        return self.ws_bytes
+
+    def launch(self, batch, k):
+        dur = self.us * 1e-6 * sum(r.limbs * (1 << r.log2n) / 65536.0 for r in batch)
+        self.launched.append((time.monotonic(), [r.rid for r in batch]))
+        return time.monotonic() + dur
+
+    def done(self, handle):
+        return time.monotonic() >= handle
+
+    def finish(self, handle):
+        pass
+
+
+def _trace(n, rate, seed=1):
+    return workloads.serving_requests(seed, n, rate)
+
+
+def test_trace_distribution():
+    tr = _trace(20000, 10000.0)
+    t = np.array([x[0] for x in tr])
+    gaps = np.diff(t)
+    assert abs(gaps.mean() * 10000.0 - 1.0) < 0.05          # Poisson at the requested rate
+    ns = np.array([x[1] for x in tr])
+    for log2n, w in zip(workloads.SERVE_LOG2N, workloads.SERVE_WEIGHTS):
+        assert abs((ns == log2n).mean() - w) < 0.02
+    Ls = np.array([x[2] for x in tr])
+    assert Ls.min() == 1 and Ls.max() == 60 and abs(Ls.mean() - 30.5) < 1.0
+
+
+def test_every_request_completes_fifo():
+    ex = FakeExecutor()
+    eng = serve.Engine(ex, budget_bytes=8 << 30, streams=3)
+    st = eng.run(_trace(400, 20000.0))
+    reqs = st["_requests"]
+    assert st["completed"] == 400 and st["rejected"] == 0
+    admits = [r.t_admit for r in reqs]
+    assert all(a <= b for a, b in zip(admits, admits[1:]))           # FIFO admission
+    assert all(r.t_done >= r.t_admit >= r.arrival - 1e-9 for r in reqs)
+    seen = [rid for _, batch in ex.launched for rid in batch]
+    assert sorted(seen) == list(range(400)) and seen == sorted(seen)  # once each, in order
+    assert st["arena_peak_bytes"] <= st["arena_bytes"]
+    assert st["max_inflight_batches"] >= 2                            # batches overlapped
+
+
+def test_tiny_budget_forces_queueing():
+    ex = FakeExecutor(us_per_product=50.0)
+    one = max(serve.footprint(n, L) for _, n, L in _trace(60, 20000.0))
+    eng = serve.Engine(ex, budget_bytes=one, streams=3)
+    st = eng.run(_trace(60, 20000.0))
+    assert st["completed"] == 60 and st["max_queue"] > 1
+    assert st["arena_peak_bytes"] <= one
+
+
+def test_oversize_rejected_not_queued_forever():
+    ex = FakeExecutor()
+    tr = _trace(80, 20000.0)
+    limit = serve.footprint(15, 60)            # anything larger than N=2^15 x 60 limbs is rejected
+    eng = serve.Engine(ex, budget_bytes=limit, streams=2)
+    st = eng.run(tr)
+    big = sum(1 for _, n, L in tr if serve.footprint(n, L) > limit)
+    assert big > 0 and st["rejected"] == big and st["completed"] == 80 - big
+
+
+def test_arena_allocator():
+    a = serve.Arena(1 << 20)
+    x = a.alloc(1000)
+    y = a.alloc(5000)
+    z = a.alloc(3000)
+    assert x and y and z and a.used == 1024 + 5120 + 3072
+    a.release(*y)
+    w = a.alloc(4000)
+    assert w[0] == y[0]                        # first fit reuses the hole
+    a.release(*x)
+    a.release(*w)
+    a.release(*z)
+    assert a.used == 0 and a.free == [(0, 1 << 20)]   # fully coalesced
+    assert a.alloc(2 << 20) is None
