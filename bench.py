@@ -343,6 +343,25 @@ def main():
                         "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
                         "what": "384 separate pm_polymul calls per step (one launch sequence each)"}
         out["batched_over_plain"] = round(value / out["plain"]["value"], 3)
+        # the fused product of Sec. III-B (Alg. 8) on the same batch
+        def fstep():
+            lib.pm_polymul_fused(da, db, dc, N, LIMBS, POLYS, qs, prm.psi_br, prm.psi_inv_br, ws)
+        for _ in range(3):
+            fstep()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        lib.pm_prof_read(reset=True)
+        lib.pm_prof_enable(True)
+        e0.record(stream)
+        reps = 20
+        for _ in range(reps):
+            fstep()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lib.pm_prof_enable(False)
+        fk = lib.pm_prof_read(reset=True)
+        out["fused"] = {"value": round(products * reps / (e0.elapsed_time(e1) / 1e3), 1), "unit": "polymul/s",
+                        "what": "pm_polymul_fused (Alg. 8: truncated NTTs + Karatsuba-fused Hadamard)",
+                        "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(fk.items())}}
         # stagewise: one launch per NTT stage, whole batch per launch
         sws = torch.empty(lib.pm_polymul_stagewise_workspace_bytes(N, LIMBS, POLYS) // 8,
                           dtype=torch.int64, device=dev)

@@ -91,7 +91,19 @@ int pm_polymul(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t N, size
                size_t polys_per_limb, const uint64_t *q, const uint64_t *psi_br,
                const uint64_t *psi_inv_br, void *workspace, pm_stream_t stream);
 
-/* Workspace bytes pm_polymul needs for this shape (0 if none). */
+/*
+ * The fused polynomial multiplication of Sec. III-B (Alg. 8): truncated merged
+ * CT NTTs of a and b (last stage omitted), the last CT stages, the pointwise
+ * product and the first GS stage fused into Alg. 7 on adjacent pairs (four
+ * products per pair, twiddle alpha^2 = (-1)^i psi_br[N/4 + i/2]), truncated
+ * merged GS NTT (first stage omitted) with halved butterflies. Same result,
+ * arguments and workspace as pm_polymul; N = 2 runs the unfused product.
+ */
+int pm_polymul_fused(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t N, size_t limbs,
+                     size_t polys_per_limb, const uint64_t *q, const uint64_t *psi_br,
+                     const uint64_t *psi_inv_br, void *workspace, pm_stream_t stream);
+
+/* Workspace bytes pm_polymul and pm_polymul_fused need for this shape (0 if none). */
 size_t pm_polymul_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
 
 /*

@@ -85,12 +85,14 @@ __device__ __forceinline__ uint32_t row_base(uint32_t t) {
 
 // Forward (CT) stages of round RHO on registers x. tw = psi_br of this limb,
 // Rr = R + r for row r of an R-row split.
-template <int LOGC, int RHO, int KIND>
+// TRUNC drops the stride-1 stage (the last of Alg. 5): the truncated CT NTT
+// of the fused product (Sec. III-B).
+template <int LOGC, int RHO, int KIND, bool TRUNC = false>
 __device__ __forceinline__ void fwd_round(uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t,
                                           const uint64_t* __restrict__ tw, uint32_t Rr,
                                           const Mod& M) {
   using G = RowGeom<LOGC>;
-  constexpr int P = G::p(RHO), HI = G::hi(RHO), LO = G::lo(RHO), EB = G::EB;
+  constexpr int P = G::p(RHO), HI = G::hi(RHO), LO = (TRUNC && G::lo(RHO) == 0) ? 1 : G::lo(RHO), EB = G::EB;
   const uint32_t th = t >> P;
 #pragma unroll
   for (int b = HI - 1; b >= LO; --b) {
@@ -110,13 +112,15 @@ __device__ __forceinline__ void fwd_round(uint64_t (&x)[RowGeom<LOGC>::E], uint3
   }
 }
 
-// Inverse (GS, halved) stages of round RHO, smallest stride first.
-template <int LOGC, int RHO, int KIND>
+// Inverse (GS, halved) stages of round RHO, smallest stride first. TRUNC drops
+// the stride-1 stage (the first of Alg. 6): the truncated GS NTT of the fused
+// product, whose first stage and its 1/2 are folded into Alg. 7.
+template <int LOGC, int RHO, int KIND, bool TRUNC = false>
 __device__ __forceinline__ void inv_round(uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t,
                                           const uint64_t* __restrict__ tw, uint32_t Rr,
                                           const Mod& M) {
   using G = RowGeom<LOGC>;
-  constexpr int P = G::p(RHO), HI = G::hi(RHO), LO = G::lo(RHO), EB = G::EB;
+  constexpr int P = G::p(RHO), HI = G::hi(RHO), LO = (TRUNC && G::lo(RHO) == 0) ? 1 : G::lo(RHO), EB = G::EB;
   const uint32_t th = t >> P;
 #pragma unroll
   for (int b = LO; b < HI; ++b) {
@@ -191,25 +195,65 @@ __device__ __forceinline__ void exchange(uint64_t* lds, uint64_t (&x)[RowGeom<LO
 
 // All row stages of the forward transform: rounds 0..NR-1. On return x holds
 // the row in the last round's layout (16 consecutive words per thread).
-template <int LOGC, int KIND, int RHO = 0>
+template <int LOGC, int KIND, int RHO = 0, bool TRUNC = false>
 __device__ __forceinline__ void fwd_rounds(uint64_t* lds, uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t,
                                            const uint64_t* __restrict__ tw, uint32_t Rr, const Mod& M) {
-  fwd_round<LOGC, RHO, KIND>(x, t, tw, Rr, M);
+  fwd_round<LOGC, RHO, KIND, TRUNC>(x, t, tw, Rr, M);
   if constexpr (RHO + 1 < RowGeom<LOGC>::NR) {
     exchange<LOGC, RHO, RHO + 1>(lds, x, t);
-    fwd_rounds<LOGC, KIND, RHO + 1>(lds, x, t, tw, Rr, M);
+    fwd_rounds<LOGC, KIND, RHO + 1, TRUNC>(lds, x, t, tw, Rr, M);
   }
 }
 
 // All row stages of the inverse transform, from the last round's layout back
 // to round 0's layout.
-template <int LOGC, int KIND, int RHO = RowGeom<LOGC>::NR - 1>
+template <int LOGC, int KIND, int RHO = RowGeom<LOGC>::NR - 1, bool TRUNC = false>
 __device__ __forceinline__ void inv_rounds(uint64_t* lds, uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t,
                                            const uint64_t* __restrict__ tw, uint32_t Rr, const Mod& M) {
-  inv_round<LOGC, RHO, KIND>(x, t, tw, Rr, M);
+  inv_round<LOGC, RHO, KIND, TRUNC>(x, t, tw, Rr, M);
   if constexpr (RHO > 0) {
     exchange<LOGC, RHO, RHO - 1>(lds, x, t);
-    inv_rounds<LOGC, KIND, RHO - 1>(lds, x, t, tw, Rr, M);
+    inv_rounds<LOGC, KIND, RHO - 1, TRUNC>(lds, x, t, tw, Rr, M);
+  }
+}
+
+// Alg. 7 on the 8 adjacent pairs (2i, 2i+1) of a thread's 16 consecutive words
+// (last-round layout): with u = a0 b0, v = a1 b1, w = (a0+a1)(b0+b1),
+//   c1 = w - u - v,  c0 = u + alpha^2 v,
+// alpha^2 = (-1)^i psi_br[N/4 + i/2] (Alg. 8): the square of the stride-1
+// twiddle is the stride-2 twiddle of the same word, index (R+r)*C/4 + idx/4,
+// and the sign is fixed per register because 16t and r*C are multiples of 4.
+// Needs C >= 4. Results overwrite x.
+template <int LOGC>
+struct FusedTw {
+  uint64_t v[RowGeom<LOGC>::E / 4 > 0 ? RowGeom<LOGC>::E / 4 : 1];
+};
+
+// The alpha^2 twiddles of a thread's pairs, loaded ahead of use.
+template <int LOGC>
+__device__ __forceinline__ FusedTw<LOGC> fused_twiddles(uint32_t t, const uint64_t* __restrict__ tw, uint32_t Rr) {
+  using G = RowGeom<LOGC>;
+  static_assert(LOGC >= 2, "the fused product needs rows of at least 4 words");
+  FusedTw<LOGC> f;
+  const uint32_t base = Rr * (1u << (LOGC - 2)) + (t << (G::EB - 2));
+#pragma unroll
+  for (int g = 0; g < G::E / 4; ++g) f.v[g] = tw[base + g];
+  return f;
+}
+
+template <int LOGC, int KIND>
+__device__ __forceinline__ void fused_hadamard(uint64_t (&x)[RowGeom<LOGC>::E], const uint64_t (&y)[RowGeom<LOGC>::E],
+                                               const FusedTw<LOGC>& f, const Mod& M) {
+  using G = RowGeom<LOGC>;
+#pragma unroll
+  for (int j = 0; j < G::E; j += 2) {
+    const uint64_t xi = f.v[j >> 2];
+    const uint64_t u = mulmod<KIND>(x[j], y[j], M);
+    const uint64_t v = mulmod<KIND>(x[j + 1], y[j + 1], M);
+    const uint64_t w = mulmod<KIND>(addmod(x[j], x[j + 1], M.q), addmod(y[j], y[j + 1], M.q), M);
+    const uint64_t z = mulmod<KIND>(v, xi, M);
+    x[j + 1] = submod(submod(w, u, M.q), v, M.q);
+    x[j] = (j & 2) ? submod(u, z, M.q) : addmod(u, z, M.q);
   }
 }
 

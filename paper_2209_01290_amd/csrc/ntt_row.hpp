@@ -6,6 +6,8 @@
 //   ROW_MUL  the row of a forward, the row of b forward, pointwise product
 //            mod q, inverse; with R = 1 this is all of Eq. 2 for one pair
 //   ROW_SQR  as ROW_MUL with b = a (one forward transform)
+//   ROW_FMUL the fused product of Sec. III-B (Alg. 8): truncated rows of a and
+//            b, Alg. 7 on adjacent pairs, truncated inverse rows
 #pragma once
 #include "ntt_device.hpp"
 #include "pm_internal.hpp"
@@ -20,15 +22,15 @@ __device__ __forceinline__ void row_task(const uint64_t* A, const uint64_t* B, u
   uint64_t x[G::E];
 #pragma unroll
   for (int j = 0; j < G::E; ++j) x[j] = 0;
-  if (MODE == ROW_FWD) {
+  if constexpr (MODE == ROW_FWD) {
     if (active) gmem_get<LOGC, 0>(A, x, t);
     fwd_rounds<LOGC, KIND>(lds, x, t, tf, Rr, M);
     if (active) gmem_put<LOGC, G::NR - 1>(Cout, x, t);
-  } else if (MODE == ROW_INV) {
+  } else if constexpr (MODE == ROW_INV) {
     if (active) gmem_get<LOGC, G::NR - 1>(A, x, t);
     inv_rounds<LOGC, KIND>(lds, x, t, ti, Rr, M);
     if (active) gmem_put<LOGC, 0>(Cout, x, t);
-  } else if (MODE == ROW_MUL) {
+  } else if constexpr (MODE == ROW_MUL) {
     if (active) gmem_get<LOGC, 0>(A, x, t);
     fwd_rounds<LOGC, KIND>(lds, x, t, tf, Rr, M);
     // keep the scheduler from overlapping the two transforms (register pressure)
@@ -42,6 +44,22 @@ __device__ __forceinline__ void row_task(const uint64_t* A, const uint64_t* B, u
 #pragma unroll
     for (int j = 0; j < G::E; ++j) x[j] = mulmod<KIND>(x[j], y[j], M);
     inv_rounds<LOGC, KIND>(lds, x, t, ti, Rr, M);
+    if (active) gmem_put<LOGC, 0>(Cout, x, t);
+  } else if constexpr (MODE == ROW_FMUL) {
+    // fused product (Alg. 8): truncated forward rows of a and b, Alg. 7 on
+    // adjacent pairs, truncated inverse rows
+    if (active) gmem_get<LOGC, 0>(A, x, t);
+    fwd_rounds<LOGC, KIND, 0, true>(lds, x, t, tf, Rr, M);
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t y[G::E];
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) y[j] = 0;
+    if (active) gmem_get<LOGC, 0>(B, y, t);
+    const FusedTw<LOGC> ftw = fused_twiddles<LOGC>(t, tf, Rr);   // in flight during b's rows
+    fwd_rounds<LOGC, KIND, 0, true>(lds, y, t, tf, Rr, M);
+    __builtin_amdgcn_sched_barrier(0);
+    fused_hadamard<LOGC, KIND>(x, y, ftw, M);
+    inv_rounds<LOGC, KIND, G::NR - 1, true>(lds, x, t, ti, Rr, M);
     if (active) gmem_put<LOGC, 0>(Cout, x, t);
   } else {  // ROW_SQR: a == b, one forward transform
     if (active) gmem_get<LOGC, 0>(A, x, t);
@@ -57,7 +75,7 @@ __device__ __forceinline__ void row_task(const uint64_t* A, const uint64_t* B, u
 // product holds a second row of 16 words and gets 3 waves per SIMD.
 template <int MODE>
 struct RowWaves {
-  static constexpr int value = MODE == ROW_MUL ? 3 : 4;   // ROW_SQR holds one row
+  static constexpr int value = (MODE == ROW_MUL || MODE == ROW_FMUL) ? 3 : 4;   // two rows held
 };
 
 }  // namespace pm

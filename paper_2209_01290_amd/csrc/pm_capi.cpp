@@ -112,8 +112,8 @@ int check_ptr(const void* p, const char* name) {
 const char* row_name(int mode, int logc) {
   static std::vector<std::string> names = [] {
     std::vector<std::string> v;
-    const char* m[4] = {"row_fwd_c", "row_inv_c", "row_mul_c", "row_sqr_c"};
-    for (int i = 0; i < 4; ++i)
+    const char* m[5] = {"row_fwd_c", "row_inv_c", "row_mul_c", "row_sqr_c", "row_fmul_c"};
+    for (int i = 0; i < 5; ++i)
       for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c));
     return v;
   }();
@@ -234,9 +234,9 @@ size_t pm_polymul_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb)
   return p.R > 1 ? N * limbs * polys_per_limb * sizeof(uint64_t) : 0;
 }
 
-int pm_polymul(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, size_t limbs,
-               size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br,
-               const uint64_t* psi_inv_br, void* workspace, pm_stream_t stream) {
+static int polymul_common(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, size_t limbs,
+                          size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br,
+                          const uint64_t* psi_inv_br, void* workspace, pm_stream_t stream, bool fused) {
   Batch b;
   int rc;
   const size_t polys = polys_per_limb;
@@ -245,13 +245,16 @@ int pm_polymul(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, siz
       (rc = check_ptr(psi_br, "psi_br")) || (rc = check_ptr(psi_inv_br, "psi_inv_br")))
     return rc;
   const PassPlan p = plan_for(OP_POLYMUL, b.log2n);
-  const bool square = (a == b_);
+  // the fused product needs N >= 4 (Alg. 8's squared-twiddle identity)
+  fused = fused && b.log2n >= 2;
+  const bool same = (a == b_);          // one operand: one column pass, no workspace
+  const bool square = same && !fused;   // and, unfused, one row transform
   // The product is commutative: when c aliases b, swap so that c aliases a.
   const uint64_t* A = a;
   const uint64_t* B = b_;
   if (c == B && c != A) std::swap(A, B);
   uint64_t* ws = (uint64_t*)workspace;
-  if (p.R > 1 && !square) {
+  if (p.R > 1 && !same) {
     if ((rc = check_ptr(workspace, "workspace"))) return rc;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -262,22 +265,35 @@ int pm_polymul(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, siz
     if (p.R == 1) {
       RowArgs ra{A + base, square ? nullptr : B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys,
                  (uint32_t)nl, &ls};
-      return run_row(p.logc, b.kind, square ? ROW_SQR : ROW_MUL, ra, s);
+      return run_row(p.logc, b.kind, fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL), ra, s);
     }
     // column stages of a (-> c) and b (-> workspace), fused rows, inverse columns of c
-    uint64_t* wb = square ? c + base : ws + base;
+    uint64_t* wb = same ? c + base : ws + base;
     ColArgs cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
-               square ? 1u : 2u, &ls};
+               same ? 1u : 2u, &ls};
     hipError_t e = run_col(p.logr, b.kind, false, cf, s);
     if (e != hipSuccess) return e;
     RowArgs ra{c + base, square ? nullptr : wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl,
                &ls};
-    if ((e = run_row(p.logc, b.kind, square ? ROW_SQR : ROW_MUL, ra, s)) != hipSuccess) return e;
+    if ((e = run_row(p.logc, b.kind, fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL), ra, s)) != hipSuccess)
+      return e;
     ColArgs ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
     return run_col(p.logr, b.kind, true, ci, s);
   });
   if (rc == PM_OK) g_err.clear();
   return rc;
+}
+
+int pm_polymul(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t N, size_t limbs, size_t polys_per_limb,
+               const uint64_t* q, const uint64_t* psi_br, const uint64_t* psi_inv_br, void* workspace,
+               pm_stream_t stream) {
+  return polymul_common(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace, stream, false);
+}
+
+int pm_polymul_fused(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t N, size_t limbs,
+                     size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br, const uint64_t* psi_inv_br,
+                     void* workspace, pm_stream_t stream) {
+  return polymul_common(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace, stream, true);
 }
 
 size_t pm_polymul_stagewise_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {

@@ -15,7 +15,7 @@ struct LimbSet {
   Mod mod[MAXL];
 };
 
-enum { ROW_FWD = 0, ROW_INV = 1, ROW_MUL = 2, ROW_SQR = 3 };
+enum { ROW_FWD = 0, ROW_INV = 1, ROW_MUL = 2, ROW_SQR = 3, ROW_FMUL = 4 };
 
 struct RowArgs {
   const uint64_t* A;      // input rows (FWD/INV: in place with C allowed)

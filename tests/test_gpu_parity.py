@@ -106,8 +106,9 @@ def test_ntt_fwd_inv(L, log2n):
     _assert_equal(L.to_host(y).reshape(a.shape), oracle_ntt_inv(a, qs, iv_o), "ntt_inv N=%d" % N)
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["eq2", "fused"])
 @pytest.mark.parametrize("log2n", ALL_LOG2N)
-def test_polymul(L, log2n):
+def test_polymul(L, log2n, fused):
     N = 1 << log2n
     limbs, polys = _limbs_for(N), 3
     qs = L.pm_ntt_primes(N, limbs)
@@ -117,11 +118,12 @@ def test_polymul(L, log2n):
     da, db = L.to_device(a), L.to_device(b)
     dc = torch_empty_like(da)
     ws = workspace(L, N, limbs, polys)
-    L.pm_polymul(da, db, dc, N, limbs, polys, qs, dfw, div, ws)
+    fn = L.pm_polymul_fused if fused else L.pm_polymul
+    fn(da, db, dc, N, limbs, polys, qs, dfw, div, ws)
     _sync()
     got = L.to_host(dc).reshape(a.shape)
     want = oracle_polymul(a, b, qs, N, fw_o, iv_o)
-    _assert_equal(got, want, "polymul N=%d" % N)
+    _assert_equal(got, want, "polymul%s N=%d" % (" fused" if fused else "", N))
     if N <= 1024:
         o = oracle.default()
         for l in range(limbs):
@@ -162,10 +164,13 @@ def test_every_pass_plan(L, log2n):
                 L.pm_tune_set(op, log2n, logc)
             dc = torch_empty_like(da)
             L.pm_polymul(da, db, dc, N, limbs, polys, qs, dfw, div, workspace(L, N, limbs, polys))
+            df = torch_empty_like(da)
+            L.pm_polymul_fused(da, db, df, N, limbs, polys, qs, dfw, div, workspace(L, N, limbs, polys))
             x = da.clone()
             L.pm_ntt_fwd(x, N, limbs, polys, qs, dfw)
             _sync()
             _assert_equal(L.to_host(dc).reshape(a.shape), want_mul, "polymul N=%d logc=%d" % (N, logc))
+            _assert_equal(L.to_host(df).reshape(a.shape), want_mul, "fused N=%d logc=%d" % (N, logc))
             _assert_equal(L.to_host(x).reshape(a.shape), want_fwd, "ntt_fwd N=%d logc=%d" % (N, logc))
             L.pm_ntt_inv(x, N, limbs, polys, qs, div)
             _sync()
@@ -192,7 +197,7 @@ def test_stagewise(L, log2n):
 
 
 @pytest.mark.parametrize("log2n", [10, 16])
-@pytest.mark.parametrize("path", ["fused", "stagewise"])
+@pytest.mark.parametrize("path", ["eq2", "stagewise", "alg8"])
 def test_aliasing(L, log2n, path):
     N = 1 << log2n
     limbs, polys = 2, 2
@@ -200,7 +205,7 @@ def test_aliasing(L, log2n, path):
     fw_o, iv_o = oracle_tables(qs, N)
     _, _, dfw, div = device_tables(qs, N)
     a, b = operands(N, qs, polys, request=400 + log2n)
-    fn = L.pm_polymul if path == "fused" else L.pm_polymul_stagewise
+    fn = {"eq2": L.pm_polymul, "stagewise": L.pm_polymul_stagewise, "alg8": L.pm_polymul_fused}[path]
     ws = workspace(L, N, limbs, polys, path == "stagewise")
     want_ab = oracle_polymul(a, b, qs, N, fw_o, iv_o)
     want_aa = oracle_polymul(a, a, qs, N, fw_o, iv_o)
