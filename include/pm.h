@@ -161,6 +161,26 @@ int pm_plan_launch(pm_plan *plan, pm_stream_t stream);
 int pm_plan_destroy(pm_plan *plan);   /* waits for the device before freeing */
 size_t pm_plan_device_bytes(const pm_plan *plan);
 
+/* ------------------------------------------------------ Barrett variant study
+ * The reductions of Sec. II-B side by side: variant 2 = classical Barrett
+ * (Alg. 2, up to two correctional subtractions), 3 = Dhem-Quisquater with
+ * alpha = N+3, beta = -2 (Alg. 3), 4 = the proposed alpha = N+1, beta = -2
+ * (Alg. 4), 0 = the built-in '%'. word_bits = 32 computes on 32-bit words
+ * (len(q) <= 30; <= 28 for Alg. 3), 64 on 64-bit words (len(q) <= 62; <= 60
+ * for Alg. 3). Inputs canonical (< q), stored as uint64 words either way.
+ *
+ * pm_reduce_apply: c[i] = a[i]*b[i] mod q and, per workgroup of 256 indices,
+ * how many reductions took 0, 1 and 2 correctional subtractions:
+ * hist[3*w + k] (device, 3 * ceil(n/256) uint32).
+ * pm_reduce_chain: throughput probe; each of `threads` threads (a positive
+ * multiple of 256) runs 8 independent chains x <- reduce(x*y) for `iters`
+ * steps and writes one word to out (device, `threads` words); 0 < y < q.
+ */
+int pm_reduce_apply(int variant, unsigned word_bits, const uint64_t *a, const uint64_t *b, uint64_t *c,
+                    uint32_t *hist, size_t n, uint64_t q, pm_stream_t stream);
+int pm_reduce_chain(int variant, unsigned word_bits, uint64_t *out, size_t threads, uint64_t y, int iters,
+                    uint64_t q, pm_stream_t stream);
+
 /* ------------------------------------------------------------------- tuning
  * Pass plan per (operation, N): an N-point transform is a column pass of
  * R = N / 2^logc rows (in registers) followed by a row pass over rows of

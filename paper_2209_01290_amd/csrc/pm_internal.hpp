@@ -55,4 +55,16 @@ struct JobDev;
 hipError_t launch_jobs(int phase, int maxlogc, int kind, const JobDev* jobs, const uint32_t* item_job,
                        uint32_t nitems, hipStream_t s);
 
+// Barrett variant study (barrett_study.hip, barrett_study_host.cpp).
+struct RedParams {
+  uint64_t q;
+  uint64_t mu;      // floor(2^(2m + e) / q) with e = 0, 3, 1 for Alg. 2, 3, 4
+  uint32_t m;       // len(q)
+  uint32_t pad;
+};
+hipError_t launch_reduce_apply(int variant, int word_bits, const uint64_t* a, const uint64_t* b, uint64_t* c,
+                               uint32_t* hist, size_t n, const RedParams& P, hipStream_t s);
+hipError_t launch_reduce_chain(int variant, int word_bits, uint64_t* out, size_t threads, uint64_t y, int iters,
+                               const RedParams& P, hipStream_t s);
+
 }  // namespace pm

@@ -78,6 +78,8 @@ def load():
             "pm_plan_launch": (i32, [vp, vp]),
             "pm_plan_destroy": (i32, [vp]),
             "pm_plan_device_bytes": (sz, [vp]),
+            "pm_reduce_apply": (i32, [i32, ctypes.c_uint, vp, vp, vp, vp, sz, u64, vp]),
+            "pm_reduce_chain": (i32, [i32, ctypes.c_uint, vp, sz, u64, i32, u64, vp]),
             "pm_prof_read": (i32, [ctypes.POINTER(ProfEntry), sz, ctypes.POINTER(sz), i32]),
         }
         for name, (res, args) in sig.items():
@@ -95,7 +97,7 @@ def exported_symbols():
             "pm_polymul_stagewise_workspace_bytes", "pm_tune_set", "pm_tune_get",
             "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read",
             "pm_polymul_jobs_workspace_bytes", "pm_polymul_jobs", "pm_plan_create", "pm_plan_launch",
-            "pm_plan_destroy", "pm_plan_device_bytes"]
+            "pm_plan_destroy", "pm_plan_device_bytes", "pm_reduce_apply", "pm_reduce_chain"]
 
 
 def _check(rc: int, func: str):
@@ -238,6 +240,21 @@ def pm_plan_destroy(plan):
 
 def pm_plan_device_bytes(plan):
     return int(load().pm_plan_device_bytes(plan))
+
+
+def pm_reduce_apply(variant, word_bits, a, b, c, hist, q, n=None, stream=None):
+    """Barrett variant study: c = a*b mod q by variant (0 = %, 2, 3, 4 = Alg. number);
+    hist (int32/uint32 device tensor, 3 per 256 indices) receives correction counts."""
+    n = a.numel() if n is None else n
+    if hist.element_size() != 4 or not hist.is_cuda or not hist.is_contiguous():
+        raise TypeError("hist must be a contiguous 32-bit device tensor")
+    _check(load().pm_reduce_apply(variant, word_bits, _dptr(a, "a"), _dptr(b, "b"), _dptr(c, "c"),
+                                  hist.data_ptr(), n, int(q), _stream(stream, a)), "pm_reduce_apply")
+
+
+def pm_reduce_chain(variant, word_bits, out, y, iters, q, stream=None):
+    _check(load().pm_reduce_chain(variant, word_bits, _dptr(out, "out"), out.numel(), int(y), iters, int(q),
+                                  _stream(stream, out)), "pm_reduce_chain")
 
 
 def pm_tune_set(op, log2n, logc):
