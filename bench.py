@@ -197,6 +197,85 @@ def mixed_batch(torch, lib, dev, launches=5):
             "batched_over_per_request": round(ms_plain / ms, 3)}
 
 
+def _median_call_us(torch, stream, fn, reps):
+    """Median device time of one call over `reps` back-to-back calls (events
+    between consecutive calls on the same stream)."""
+    for _ in range(5):
+        fn()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(reps):
+        fn()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    return pct([ev[k].elapsed_time(ev[k + 1]) * 1e3 for k in range(reps)], 50)
+
+
+def words32(torch, lib, dev, steps=20):
+    """The 32-bit word path (moduli up to 30 bits, Alg. 4 with beta = 32):
+    single-transform latency at N = 2^14 and 2^16 beside 62-bit moduli on
+    64-bit words (the rows of the paper's comparison table in Sec. VII), and the workload-size
+    trade-off: the 2880-bit modulus of the headline workload as 96 30-bit
+    limbs on 32-bit words against 48 60-bit limbs on 64-bit words."""
+    from paper_2209_01290_amd import synth
+    stream = torch.cuda.current_stream(dev)
+    lat = []
+    for log2n in (14, 16):
+        N = 1 << log2n
+        for bits in (30, 62):
+            if bits <= 30:
+                prm = lib.Params32(N, 1, bits=bits, device=dev)
+                a, _ = synth.operands(SEED + 10, prm.q, 1, N)
+                x = lib.to_device32(a, dev)
+                fwd = lambda: lib.pm_ntt_fwd_u32(x, N, 1, 1, prm.q, prm.psi_br)
+                inv = lambda: lib.pm_ntt_inv_u32(x, N, 1, 1, prm.q, prm.psi_inv_br)
+            else:
+                prm = lib.Params(N, 1, bits=bits, device=dev)
+                a, _ = synth.operands(SEED + 10, prm.q, 1, N)
+                x = lib.to_device(a, dev)
+                fwd = lambda: lib.pm_ntt_fwd(x, N, 1, 1, prm.q, prm.psi_br)
+                inv = lambda: lib.pm_ntt_inv(x, N, 1, 1, prm.q, prm.psi_inv_br)
+            lat.append({"N": N, "q_bits": bits, "word_bits": 32 if bits <= 30 else 64,
+                        "ntt_us": round(_median_call_us(torch, stream, fwd, 200), 2),
+                        "intt_us": round(_median_call_us(torch, stream, inv, 200), 2)})
+    # same 2880-bit Q at N = 2^16, 8 pairs: 96 x 30-bit limbs on 32-bit words
+    N, L32, P = 1 << 16, 96, POLYS
+    prm = lib.Params32(N, L32, bits=30, device=dev)
+    a, b = synth.operands(SEED + 11, prm.q, P, N)
+    da, db = lib.to_device32(a, dev), lib.to_device32(b, dev)
+    dc = torch.empty_like(da)
+    wsb = lib.pm_polymul_u32_workspace_bytes(N, L32, P)
+    ws = torch.empty(max(wsb // 4, 1), dtype=torch.int32, device=dev)
+
+    def step():
+        lib.pm_polymul_u32(da, db, dc, N, L32, P, prm.q, prm.psi_br, prm.psi_inv_br, ws)
+
+    for _ in range(3):
+        step()
+    lib.pm_prof_read(reset=True)
+    lib.pm_prof_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lib.pm_prof_enable(False)
+    k32 = lib.pm_prof_read(reset=True)
+    ms = e0.elapsed_time(e1) / steps
+    x = da.clone()
+    ntt_us = _median_call_us(torch, stream, lambda: lib.pm_ntt_fwd_u32(x, N, L32, P, prm.q, prm.psi_br), 20)
+    return {"what": "32-bit words, moduli < 2^30 (Alg. 4, beta = 32)",
+            "single_transform_latency": lat,
+            "polymul_96x30bit_limbs": {
+                "limbs": L32, "polys_per_limb": P, "ms_per_step": round(ms, 4),
+                "limb_products_per_s": round(L32 * P / ms * 1e3, 1),
+                "q2880_products_per_s": round(P / ms * 1e3, 1),
+                "ntt_fwd_per_s": round(L32 * P / ntt_us * 1e6, 1),
+                "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(k32.items())}}}
+
+
 def serving(lib, rates=(5000.0, 20000.0, 50000.0), nreq=4000):
     """The continuous-batching loop on Poisson arrivals (N in 2^13..2^17,
     1..60 limbs): throughput and p50/p99 latency per offered rate."""
@@ -393,6 +472,10 @@ def main():
         step()
         torch.cuda.synchronize()
         out["mixed_batch"] = mixed_batch(torch, lib, dev)
+        w32 = words32(torch, lib, dev)
+        w32["polymul_96x30bit_limbs"]["vs_48x60bit_limbs_u64"] = round(
+            w32["polymul_96x30bit_limbs"]["q2880_products_per_s"] / (value / LIMBS), 3)
+        out["words32"] = w32
         out["serving"] = serving(lib)
 
     if not args.no_cpu:

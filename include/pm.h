@@ -118,6 +118,45 @@ int pm_polymul_stagewise(const uint64_t *a, const uint64_t *b, uint64_t *c, size
                          const uint64_t *psi_inv_br, void *workspace, pm_stream_t stream);
 size_t pm_polymul_stagewise_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
 
+/* --------------------------------------------------- interleaved layout
+ * The storage of the paper's throughput-optimised multi-block design
+ * (Sec. V-C): the batch of one limb is an N x P matrix held coefficient-major,
+ * coefficient j of polynomial p at [j * P + p] (P = polys_per_limb), so that
+ * consecutive lanes read consecutive words at every stage. x, a, b, c: device
+ * [limbs][N][polys_per_limb]. Same transforms, product, tables, limits,
+ * aliasing, stream and error rules as pm_ntt_fwd, pm_ntt_inv and pm_polymul;
+ * with polys_per_limb = 1 the layouts coincide. pm_polymul_il's workspace:
+ * pm_polymul_il_workspace_bytes() bytes (NULL when 0 or when a == b).
+ */
+int pm_ntt_fwd_il(uint64_t *x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t *q,
+                  const uint64_t *psi_br, pm_stream_t stream);
+int pm_ntt_inv_il(uint64_t *x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t *q,
+                  const uint64_t *psi_inv_br, pm_stream_t stream);
+int pm_polymul_il(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t N, size_t limbs,
+                  size_t polys_per_limb, const uint64_t *q, const uint64_t *psi_br,
+                  const uint64_t *psi_inv_br, void *workspace, pm_stream_t stream);
+size_t pm_polymul_il_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
+
+/* --------------------------------------------------------- 32-bit words
+ * The paper's 30-bit NTT timings (Sec. VII, comparison table) use 32-bit words:
+ * Alg. 4 with beta = 32 needs len(q) <= 30. These calls are pm_ntt_fwd,
+ * pm_ntt_inv and pm_polymul on 32-bit words, with the same layouts, aliasing,
+ * stream and error rules, for moduli q odd with 3 <= q < 2^30 and 2N | q - 1.
+ * x, a, b, c, psi_br, psi_inv_br: device arrays of uint32_t, 4-byte aligned;
+ * q: host array of limbs moduli. pm_make_tables_u32 writes the twiddle tables
+ * as 32-bit words (host arrays of N words).
+ */
+int pm_ntt_fwd_u32(uint32_t *x, size_t N, size_t limbs, size_t polys_per_limb, const uint32_t *q,
+                   const uint32_t *psi_br, pm_stream_t stream);
+int pm_ntt_inv_u32(uint32_t *x, size_t N, size_t limbs, size_t polys_per_limb, const uint32_t *q,
+                   const uint32_t *psi_inv_br, pm_stream_t stream);
+int pm_polymul_u32(const uint32_t *a, const uint32_t *b, uint32_t *c, size_t N, size_t limbs,
+                   size_t polys_per_limb, const uint32_t *q, const uint32_t *psi_br,
+                   const uint32_t *psi_inv_br, void *workspace, pm_stream_t stream);
+/* Workspace bytes pm_polymul_u32 needs for this shape (0 if none). */
+size_t pm_polymul_u32_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
+int pm_make_tables_u32(uint32_t q, size_t N, uint32_t psi, uint32_t *psi_br, uint32_t *psi_inv_br);
+
 /* ---------------------------------------------------------- batched jobs
  * A job is `count` polynomial pairs sharing N = 2^log2n and modulus q:
  * c[i] = a[i] (*) b[i] for i < count, each array count*N words (device).

@@ -25,6 +25,7 @@
 // in registers and runs the s column stages; twiddles are uniform per launch.
 #pragma once
 #include "modarith.hpp"
+#include "modarith32.hpp"
 
 namespace pm {
 
@@ -87,10 +88,9 @@ __device__ __forceinline__ uint32_t row_base(uint32_t t) {
 // Rr = R + r for row r of an R-row split.
 // TRUNC drops the stride-1 stage (the last of Alg. 5): the truncated CT NTT
 // of the fused product (Sec. III-B).
-template <int LOGC, int RHO, int KIND, bool TRUNC = false>
-__device__ __forceinline__ void fwd_round(uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t,
-                                          const uint64_t* __restrict__ tw, uint32_t Rr,
-                                          const Mod& M) {
+template <int LOGC, int RHO, int KIND, bool TRUNC = false, typename W, typename MT>
+__device__ __forceinline__ void fwd_round(W (&x)[RowGeom<LOGC>::E], uint32_t t, const W* __restrict__ tw,
+                                          uint32_t Rr, const MT& M) {
   using G = RowGeom<LOGC>;
   constexpr int P = G::p(RHO), HI = G::hi(RHO), LO = (TRUNC && G::lo(RHO) == 0) ? 1 : G::lo(RHO), EB = G::EB;
   const uint32_t th = t >> P;
@@ -101,7 +101,7 @@ __device__ __forceinline__ void fwd_round(uint64_t (&x)[RowGeom<LOGC>::E], uint3
     const uint32_t base = Rr * mm + (th << (P + EB - b - 1));
 #pragma unroll
     for (int g = 0; g < (G::E >> (jb + 1)); ++g) {
-      const uint64_t xi = tw[base + g];
+      const W xi = tw[base + g];
 #pragma unroll
       for (int s = 0; s < (1 << jb); ++s) {
         const int j = (g << (jb + 1)) | s;
@@ -115,10 +115,9 @@ __device__ __forceinline__ void fwd_round(uint64_t (&x)[RowGeom<LOGC>::E], uint3
 // Inverse (GS, halved) stages of round RHO, smallest stride first. TRUNC drops
 // the stride-1 stage (the first of Alg. 6): the truncated GS NTT of the fused
 // product, whose first stage and its 1/2 are folded into Alg. 7.
-template <int LOGC, int RHO, int KIND, bool TRUNC = false>
-__device__ __forceinline__ void inv_round(uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t,
-                                          const uint64_t* __restrict__ tw, uint32_t Rr,
-                                          const Mod& M) {
+template <int LOGC, int RHO, int KIND, bool TRUNC = false, typename W, typename MT>
+__device__ __forceinline__ void inv_round(W (&x)[RowGeom<LOGC>::E], uint32_t t, const W* __restrict__ tw,
+                                          uint32_t Rr, const MT& M) {
   using G = RowGeom<LOGC>;
   constexpr int P = G::p(RHO), HI = G::hi(RHO), LO = (TRUNC && G::lo(RHO) == 0) ? 1 : G::lo(RHO), EB = G::EB;
   const uint32_t th = t >> P;
@@ -129,7 +128,7 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[RowGeom<LOGC>::E], uint3
     const uint32_t base = Rr * mm + (th << (P + EB - b - 1));
 #pragma unroll
     for (int g = 0; g < (G::E >> (jb + 1)); ++g) {
-      const uint64_t xi = tw[base + g];
+      const W xi = tw[base + g];
 #pragma unroll
       for (int s = 0; s < (1 << jb); ++s) {
         const int j = (g << (jb + 1)) | s;
@@ -145,27 +144,26 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[RowGeom<LOGC>::E], uint3
 // LOGC <= 4 the single round has P = 0 and EB = LOGC, and the same formulas
 // hold with 2^(P+4) replaced by 2^EB, which row_base/lds_base never need
 // because th = 0 there (one thread per row).
-template <int LOGC, int RHO>
-__device__ __forceinline__ void lds_put(uint64_t* lds, const uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t) {
+template <int LOGC, int RHO, typename W>
+__device__ __forceinline__ void lds_put(W* lds, const W (&x)[RowGeom<LOGC>::E], uint32_t t) {
   using G = RowGeom<LOGC>;
   constexpr int P = G::p(RHO);
-  uint64_t* b = lds + lds_base<P>(t);
+  W* b = lds + lds_base<P>(t);
 #pragma unroll
   for (int j = 0; j < G::E; ++j) b[lds_off<P>(j)] = x[j];
 }
 
-template <int LOGC, int RHO>
-__device__ __forceinline__ void lds_get(const uint64_t* lds, uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t) {
+template <int LOGC, int RHO, typename W>
+__device__ __forceinline__ void lds_get(const W* lds, W (&x)[RowGeom<LOGC>::E], uint32_t t) {
   using G = RowGeom<LOGC>;
   constexpr int P = G::p(RHO);
-  const uint64_t* b = lds + lds_base<P>(t);
+  const W* b = lds + lds_base<P>(t);
 #pragma unroll
   for (int j = 0; j < G::E; ++j) x[j] = b[lds_off<P>(j)];
 }
 
-template <int LOGC, int RHO>
-__device__ __forceinline__ void gmem_get(const uint64_t* __restrict__ row, uint64_t (&x)[RowGeom<LOGC>::E],
-                                         uint32_t t) {
+template <int LOGC, int RHO, typename W>
+__device__ __forceinline__ void gmem_get(const W* __restrict__ row, W (&x)[RowGeom<LOGC>::E], uint32_t t) {
   using G = RowGeom<LOGC>;
   constexpr int P = G::p(RHO);
   const uint32_t tb = (G::NR > 1) ? row_base<P>(t) : (t << G::EB);
@@ -173,9 +171,8 @@ __device__ __forceinline__ void gmem_get(const uint64_t* __restrict__ row, uint6
   for (int j = 0; j < G::E; ++j) x[j] = (row + (j << P))[tb];
 }
 
-template <int LOGC, int RHO>
-__device__ __forceinline__ void gmem_put(uint64_t* __restrict__ row, const uint64_t (&x)[RowGeom<LOGC>::E],
-                                         uint32_t t) {
+template <int LOGC, int RHO, typename W>
+__device__ __forceinline__ void gmem_put(W* __restrict__ row, const W (&x)[RowGeom<LOGC>::E], uint32_t t) {
   using G = RowGeom<LOGC>;
   constexpr int P = G::p(RHO);
   const uint32_t tb = (G::NR > 1) ? row_base<P>(t) : (t << G::EB);
@@ -185,8 +182,8 @@ __device__ __forceinline__ void gmem_put(uint64_t* __restrict__ row, const uint6
 
 // Move registers from round FROM's layout to round TO's layout through LDS.
 // All threads of the workgroup must call it (it holds two barriers).
-template <int LOGC, int FROM, int TO>
-__device__ __forceinline__ void exchange(uint64_t* lds, uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t) {
+template <int LOGC, int FROM, int TO, typename W>
+__device__ __forceinline__ void exchange(W* lds, W (&x)[RowGeom<LOGC>::E], uint32_t t) {
   __syncthreads();
   lds_put<LOGC, FROM>(lds, x, t);
   __syncthreads();
@@ -195,9 +192,9 @@ __device__ __forceinline__ void exchange(uint64_t* lds, uint64_t (&x)[RowGeom<LO
 
 // All row stages of the forward transform: rounds 0..NR-1. On return x holds
 // the row in the last round's layout (16 consecutive words per thread).
-template <int LOGC, int KIND, int RHO = 0, bool TRUNC = false>
-__device__ __forceinline__ void fwd_rounds(uint64_t* lds, uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t,
-                                           const uint64_t* __restrict__ tw, uint32_t Rr, const Mod& M) {
+template <int LOGC, int KIND, int RHO = 0, bool TRUNC = false, typename W, typename MT>
+__device__ __forceinline__ void fwd_rounds(W* lds, W (&x)[RowGeom<LOGC>::E], uint32_t t, const W* __restrict__ tw,
+                                           uint32_t Rr, const MT& M) {
   fwd_round<LOGC, RHO, KIND, TRUNC>(x, t, tw, Rr, M);
   if constexpr (RHO + 1 < RowGeom<LOGC>::NR) {
     exchange<LOGC, RHO, RHO + 1>(lds, x, t);
@@ -207,9 +204,9 @@ __device__ __forceinline__ void fwd_rounds(uint64_t* lds, uint64_t (&x)[RowGeom<
 
 // All row stages of the inverse transform, from the last round's layout back
 // to round 0's layout.
-template <int LOGC, int KIND, int RHO = RowGeom<LOGC>::NR - 1, bool TRUNC = false>
-__device__ __forceinline__ void inv_rounds(uint64_t* lds, uint64_t (&x)[RowGeom<LOGC>::E], uint32_t t,
-                                           const uint64_t* __restrict__ tw, uint32_t Rr, const Mod& M) {
+template <int LOGC, int KIND, int RHO = RowGeom<LOGC>::NR - 1, bool TRUNC = false, typename W, typename MT>
+__device__ __forceinline__ void inv_rounds(W* lds, W (&x)[RowGeom<LOGC>::E], uint32_t t, const W* __restrict__ tw,
+                                           uint32_t Rr, const MT& M) {
   inv_round<LOGC, RHO, KIND, TRUNC>(x, t, tw, Rr, M);
   if constexpr (RHO > 0) {
     exchange<LOGC, RHO, RHO - 1>(lds, x, t);
@@ -224,64 +221,101 @@ __device__ __forceinline__ void inv_rounds(uint64_t* lds, uint64_t (&x)[RowGeom<
 // twiddle is the stride-2 twiddle of the same word, index (R+r)*C/4 + idx/4,
 // and the sign is fixed per register because 16t and r*C are multiples of 4.
 // Needs C >= 4. Results overwrite x.
-template <int LOGC>
+template <int LOGC, typename W>
 struct FusedTw {
-  uint64_t v[RowGeom<LOGC>::E / 4 > 0 ? RowGeom<LOGC>::E / 4 : 1];
+  W v[RowGeom<LOGC>::E / 4 > 0 ? RowGeom<LOGC>::E / 4 : 1];
 };
 
 // The alpha^2 twiddles of a thread's pairs, loaded ahead of use.
-template <int LOGC>
-__device__ __forceinline__ FusedTw<LOGC> fused_twiddles(uint32_t t, const uint64_t* __restrict__ tw, uint32_t Rr) {
+template <int LOGC, typename W>
+__device__ __forceinline__ FusedTw<LOGC, W> fused_twiddles(uint32_t t, const W* __restrict__ tw, uint32_t Rr) {
   using G = RowGeom<LOGC>;
   static_assert(LOGC >= 2, "the fused product needs rows of at least 4 words");
-  FusedTw<LOGC> f;
+  FusedTw<LOGC, W> f;
   const uint32_t base = Rr * (1u << (LOGC - 2)) + (t << (G::EB - 2));
 #pragma unroll
   for (int g = 0; g < G::E / 4; ++g) f.v[g] = tw[base + g];
   return f;
 }
 
-template <int LOGC, int KIND>
-__device__ __forceinline__ void fused_hadamard(uint64_t (&x)[RowGeom<LOGC>::E], const uint64_t (&y)[RowGeom<LOGC>::E],
-                                               const FusedTw<LOGC>& f, const Mod& M) {
+template <int LOGC, int KIND, typename W, typename MT>
+__device__ __forceinline__ void fused_hadamard(W (&x)[RowGeom<LOGC>::E], const W (&y)[RowGeom<LOGC>::E],
+                                               const FusedTw<LOGC, W>& f, const MT& M) {
   using G = RowGeom<LOGC>;
 #pragma unroll
   for (int j = 0; j < G::E; j += 2) {
-    const uint64_t xi = f.v[j >> 2];
-    const uint64_t u = mulmod<KIND>(x[j], y[j], M);
-    const uint64_t v = mulmod<KIND>(x[j + 1], y[j + 1], M);
-    const uint64_t w = mulmod<KIND>(addmod(x[j], x[j + 1], M.q), addmod(y[j], y[j + 1], M.q), M);
-    const uint64_t z = mulmod<KIND>(v, xi, M);
+    const W xi = f.v[j >> 2];
+    const W u = mulmod<KIND>(x[j], y[j], M);
+    const W v = mulmod<KIND>(x[j + 1], y[j + 1], M);
+    const W w = mulmod<KIND>(addmod(x[j], x[j + 1], M.q), addmod(y[j], y[j + 1], M.q), M);
+    const W z = mulmod<KIND>(v, xi, M);
     x[j + 1] = submod(submod(w, u, M.q), v, M.q);
     x[j] = (j & 2) ? submod(u, z, M.q) : addmod(u, z, M.q);
   }
 }
 
 // Column pass: R = 2^LOGR words of one column (stride C) in registers.
-template <int LOGR, int KIND>
-__device__ __forceinline__ void col_fwd(uint64_t (&x)[1 << LOGR], const uint64_t* __restrict__ tw, const Mod& M) {
+template <int LOGR, int KIND, typename W, typename MT>
+__device__ __forceinline__ void col_fwd(W (&x)[1 << LOGR], const W* __restrict__ tw, const MT& M) {
   constexpr int R = 1 << LOGR;
 #pragma unroll
   for (int lm = 0; lm < LOGR; ++lm) {
     const int m = 1 << lm, k = R >> (lm + 1);
 #pragma unroll
     for (int g = 0; g < m; ++g) {
-      const uint64_t xi = tw[m + g];
+      const W xi = tw[m + g];
 #pragma unroll
       for (int s = 0; s < k; ++s) ct_bfly<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xi, M);
     }
   }
 }
 
-template <int LOGR, int KIND>
-__device__ __forceinline__ void col_inv(uint64_t (&x)[1 << LOGR], const uint64_t* __restrict__ tw, const Mod& M) {
+template <int LOGR, int KIND, typename W, typename MT>
+__device__ __forceinline__ void col_inv(W (&x)[1 << LOGR], const W* __restrict__ tw, const MT& M) {
   constexpr int R = 1 << LOGR;
 #pragma unroll
   for (int lm = LOGR - 1; lm >= 0; --lm) {
     const int m = 1 << lm, k = R >> (lm + 1);
 #pragma unroll
     for (int g = 0; g < m; ++g) {
-      const uint64_t xi = tw[m + g];
+      const W xi = tw[m + g];
+#pragma unroll
+      for (int s = 0; s < k; ++s) gs_bfly_half<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xi, M);
+    }
+  }
+}
+
+// The same radix-2^LOGR block at any depth of Alg. 5 / Alg. 6. A block of
+// stages s0..s0+LOGR-1 touches 2^LOGR words at stride N >> (s0+LOGR) that
+// share the index bits above bit log2(N) - s0; with h those high bits and
+// rb = 2^s0 + h, stage s0+j's group g (within the block) uses the twiddle at
+// (rb << j) + g. col_fwd / col_inv are the case rb = 1.
+template <int LOGR, int KIND, typename W, typename MT>
+__device__ __forceinline__ void blk_fwd(W (&x)[1 << LOGR], const W* __restrict__ tw, uint32_t rb, const MT& M) {
+  constexpr int R = 1 << LOGR;
+#pragma unroll
+  for (int lm = 0; lm < LOGR; ++lm) {
+    const int m = 1 << lm, k = R >> (lm + 1);
+    const W* t = tw + (rb << lm);
+#pragma unroll
+    for (int g = 0; g < m; ++g) {
+      const W xi = t[g];
+#pragma unroll
+      for (int s = 0; s < k; ++s) ct_bfly<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xi, M);
+    }
+  }
+}
+
+template <int LOGR, int KIND, typename W, typename MT>
+__device__ __forceinline__ void blk_inv(W (&x)[1 << LOGR], const W* __restrict__ tw, uint32_t rb, const MT& M) {
+  constexpr int R = 1 << LOGR;
+#pragma unroll
+  for (int lm = LOGR - 1; lm >= 0; --lm) {
+    const int m = 1 << lm, k = R >> (lm + 1);
+    const W* t = tw + (rb << lm);
+#pragma unroll
+    for (int g = 0; g < m; ++g) {
+      const W xi = t[g];
 #pragma unroll
       for (int s = 0; s < k; ++s) gs_bfly_half<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xi, M);
     }

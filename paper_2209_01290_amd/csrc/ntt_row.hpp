@@ -14,12 +14,11 @@
 
 namespace pm {
 
-template <int LOGC, int KIND, int MODE>
-__device__ __forceinline__ void row_task(const uint64_t* A, const uint64_t* B, uint64_t* Cout,
-                                         const uint64_t* tf, const uint64_t* ti,
-                                         uint32_t Rr, bool active, const Mod& M, uint64_t* lds, uint32_t t) {
+template <int LOGC, int KIND, int MODE, typename W, typename MT>
+__device__ __forceinline__ void row_task(const W* A, const W* B, W* Cout, const W* tf, const W* ti, uint32_t Rr,
+                                         bool active, const MT& M, W* lds, uint32_t t) {
   using G = RowGeom<LOGC>;
-  uint64_t x[G::E];
+  W x[G::E];
 #pragma unroll
   for (int j = 0; j < G::E; ++j) x[j] = 0;
   if constexpr (MODE == ROW_FWD) {
@@ -35,7 +34,7 @@ __device__ __forceinline__ void row_task(const uint64_t* A, const uint64_t* B, u
     fwd_rounds<LOGC, KIND>(lds, x, t, tf, Rr, M);
     // keep the scheduler from overlapping the two transforms (register pressure)
     __builtin_amdgcn_sched_barrier(0);
-    uint64_t y[G::E];
+    W y[G::E];
 #pragma unroll
     for (int j = 0; j < G::E; ++j) y[j] = 0;
     if (active) gmem_get<LOGC, 0>(B, y, t);
@@ -51,11 +50,11 @@ __device__ __forceinline__ void row_task(const uint64_t* A, const uint64_t* B, u
     if (active) gmem_get<LOGC, 0>(A, x, t);
     fwd_rounds<LOGC, KIND, 0, true>(lds, x, t, tf, Rr, M);
     __builtin_amdgcn_sched_barrier(0);
-    uint64_t y[G::E];
+    W y[G::E];
 #pragma unroll
     for (int j = 0; j < G::E; ++j) y[j] = 0;
     if (active) gmem_get<LOGC, 0>(B, y, t);
-    const FusedTw<LOGC> ftw = fused_twiddles<LOGC>(t, tf, Rr);   // in flight during b's rows
+    const FusedTw<LOGC, W> ftw = fused_twiddles<LOGC>(t, tf, Rr);   // in flight during b's rows
     fwd_rounds<LOGC, KIND, 0, true>(lds, y, t, tf, Rr, M);
     __builtin_amdgcn_sched_barrier(0);
     fused_hadamard<LOGC, KIND>(x, y, ftw, M);

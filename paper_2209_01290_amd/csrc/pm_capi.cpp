@@ -70,6 +70,30 @@ int mod_kind(const Mod& M) {
   return (m >= 34 && m <= 61) ? KIND_WIDE : KIND_ANY;
 }
 
+// Barrett constants of Alg. 4 with beta = 32 (see modarith32.hpp): for an odd
+// q of m <= 30 bits, mu = floor(2^(2m+1)/q) < 2^(m+2) <= 2^32, kept as
+// mu << (29-m) for m <= 29 and as mu with one extra final shift for m = 30.
+bool make_mod32(uint32_t q, Mod32* M) {
+  if (q < 3 || !(q & 1) || (q >> 30)) return false;
+  const int m = 32 - __builtin_clz(q);
+  const uint64_t mu = ((uint64_t)1 << (2 * m + 1)) / q;
+  M->q = q;
+  M->half = (q >> 1) + 1;
+  M->s = (uint32_t)(m - 2);
+  if (m <= 29) {
+    M->mu = (uint32_t)(mu << (29 - m));
+    M->t = 0;
+  } else {
+    M->mu = (uint32_t)mu;
+    M->t = 1;
+  }
+  M->pad = 0;
+  return true;
+}
+
+// KIND_WIDE on 32-bit words: every modulus has m <= 29 (no final shift).
+int mod_kind32(const Mod32& M) { return M.t ? KIND_ANY : KIND_WIDE; }
+
 }  // namespace pm
 
 namespace {
@@ -155,6 +179,84 @@ hipError_t run_pointwise(int kind, const uint64_t* A, const uint64_t* B, uint64_
 template <class F>
 int for_chunks(const Batch& b, F f) {
   LimbSet ls;
+  for (size_t l0 = 0; l0 < b.limbs; l0 += MAXL) {
+    const size_t nl = std::min((size_t)MAXL, b.limbs - l0);
+    std::memset(&ls, 0, sizeof(ls));
+    for (size_t i = 0; i < nl; ++i) ls.mod[i] = b.mods[l0 + i];
+    hipError_t e = f(l0, nl, ls);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  return PM_OK;
+}
+
+// ---- 32-bit words
+struct Batch32 {
+  size_t N, limbs, polys;
+  unsigned log2n;
+  std::vector<Mod32> mods;
+  int kind;
+};
+
+int check_batch32(Batch32* b, size_t N, size_t limbs, size_t polys, const uint32_t* q) {
+  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N))
+    return fail(PM_EINVAL, "N must be a power of two in [2, 2^17], got " + std::to_string(N));
+  if (limbs == 0 || polys == 0) return fail(PM_EINVAL, "limbs and polys_per_limb must be positive");
+  if (polys > 65535) return fail(PM_EINVAL, "polys_per_limb above 65535 is not supported");
+  if (!q) return fail(PM_EINVAL, "q (host array of limbs moduli) is null");
+  b->N = N; b->limbs = limbs; b->polys = polys; b->log2n = log2u(N);
+  b->mods.resize(limbs);
+  b->kind = KIND_WIDE;
+  for (size_t l = 0; l < limbs; ++l) {
+    const uint32_t ql = q[l];
+    if (!make_mod32(ql, &b->mods[l]))
+      return fail(PM_EINVAL, "limb " + std::to_string(l) + ": q must be odd with 3 <= q < 2^30");
+    if ((ql - 1) % (2 * (uint64_t)N) != 0)
+      return fail(PM_EINVAL, "limb " + std::to_string(l) + ": 2N must divide q - 1");
+    if (mod_kind32(b->mods[l]) != KIND_WIDE) b->kind = KIND_ANY;
+  }
+  return PM_OK;
+}
+
+int check_ptr32(const void* p, const char* name) {
+  if (!p) return fail(PM_EINVAL, std::string(name) + " is null");
+  if ((uintptr_t)p & 3u) return fail(PM_EINVAL, std::string(name) + " is not 4-byte aligned");
+  return PM_OK;
+}
+
+const char* row_name32(int mode, int logc) {
+  static std::vector<std::string> names = [] {
+    std::vector<std::string> v;
+    const char* m[3] = {"row32_fwd_c", "row32_inv_c", "row32_mul_c"};
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c));
+    return v;
+  }();
+  return names[mode * 15 + logc].c_str();
+}
+
+const char* col_name32(bool inv, int logr) {
+  static std::vector<std::string> names = [] {
+    std::vector<std::string> v;
+    for (int i = 0; i < 2; ++i)
+      for (int r = 0; r <= 5; ++r) v.push_back(std::string(i ? "col32_inv_r" : "col32_fwd_r") + std::to_string(r));
+    return v;
+  }();
+  return names[(inv ? 6 : 0) + logr].c_str();
+}
+
+hipError_t run_row32(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s) {
+  ProfScope ps(s, row_name32(mode, logc));
+  return launch_row(logc, kind, mode, a, s);
+}
+
+hipError_t run_col32(int logr, int kind, bool inv, const ColArgsT<uint32_t>& a, hipStream_t s) {
+  ProfScope ps(s, col_name32(inv, logr));
+  return launch_col(logr, kind, inv, a, s);
+}
+
+template <class F>
+int for_chunks32(const Batch32& b, F f) {
+  LimbSet32 ls;
   for (size_t l0 = 0; l0 < b.limbs; l0 += MAXL) {
     const size_t nl = std::min((size_t)MAXL, b.limbs - l0);
     std::memset(&ls, 0, sizeof(ls));
@@ -341,6 +443,226 @@ int pm_polymul_stagewise(const uint64_t* a, const uint64_t* b_, uint64_t* c, siz
   return rc;
 }
 
+// ---------------------------------------------------------- 32-bit words --
+// The same merged transforms and Eq. 2 product on 32-bit words, for moduli of
+// up to 30 bits (Alg. 4 with beta = 32), with the pass plan of the 64-bit path.
+
+static int ntt_common32(uint32_t* x, size_t N, size_t limbs, size_t polys, const uint32_t* q,
+                        const uint32_t* tw, pm_stream_t stream, bool inv) {
+  Batch32 b;
+  int rc;
+  if ((rc = check_batch32(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr32(x, "x")) || (rc = check_ptr32(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
+  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n);
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks32(b, [&](size_t l0, size_t nl, const LimbSet32& ls) -> hipError_t {
+    uint32_t* xs = x + l0 * polys * N;
+    const uint32_t* t = tw + l0 * N;
+    RowArgsT<uint32_t> ra{xs, nullptr, xs, inv ? nullptr : t, inv ? t : nullptr, b.log2n, p.R, (uint32_t)polys,
+                          (uint32_t)nl, &ls};
+    ColArgsT<uint32_t> ca{xs, xs, nullptr, nullptr, t, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+    hipError_t e;
+    if (!inv) {
+      if (p.R > 1 && (e = run_col32(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
+      return run_row32(p.logc, b.kind, ROW_FWD, ra, s);
+    }
+    if ((e = run_row32(p.logc, b.kind, ROW_INV, ra, s)) != hipSuccess) return e;
+    if (p.R > 1) return run_col32(p.logr, b.kind, true, ca, s);
+    return hipSuccess;
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
+}
+
+int pm_ntt_fwd_u32(uint32_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint32_t* q,
+                   const uint32_t* psi_br, pm_stream_t stream) {
+  return ntt_common32(x, N, limbs, polys_per_limb, q, psi_br, stream, false);
+}
+
+int pm_ntt_inv_u32(uint32_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint32_t* q,
+                   const uint32_t* psi_inv_br, pm_stream_t stream) {
+  return ntt_common32(x, N, limbs, polys_per_limb, q, psi_inv_br, stream, true);
+}
+
+size_t pm_polymul_u32_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {
+  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N)) return 0;
+  const PassPlan p = plan_for(OP_POLYMUL, log2u(N));
+  return p.R > 1 ? N * limbs * polys_per_limb * sizeof(uint32_t) : 0;
+}
+
+int pm_polymul_u32(const uint32_t* a, const uint32_t* b_, uint32_t* c, size_t N, size_t limbs,
+                   size_t polys_per_limb, const uint32_t* q, const uint32_t* psi_br, const uint32_t* psi_inv_br,
+                   void* workspace, pm_stream_t stream) {
+  Batch32 b;
+  int rc;
+  const size_t polys = polys_per_limb;
+  if ((rc = check_batch32(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr32(a, "a")) || (rc = check_ptr32(b_, "b")) || (rc = check_ptr32(c, "c")) ||
+      (rc = check_ptr32(psi_br, "psi_br")) || (rc = check_ptr32(psi_inv_br, "psi_inv_br")))
+    return rc;
+  const PassPlan p = plan_for(OP_POLYMUL, b.log2n);
+  const bool same = (a == b_);          // one operand: one column pass, no workspace
+  const uint32_t* A = a;
+  const uint32_t* B = b_;
+  if (c == B && c != A) std::swap(A, B);
+  if (p.R > 1 && !same && (rc = check_ptr32(workspace, "workspace"))) return rc;
+  uint32_t* ws = (uint32_t*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks32(b, [&](size_t l0, size_t nl, const LimbSet32& ls) -> hipError_t {
+    const size_t base = l0 * polys * N;
+    const uint32_t* tf = psi_br + l0 * N;
+    const uint32_t* ti = psi_inv_br + l0 * N;
+    if (p.R == 1) {
+      RowArgsT<uint32_t> ra{A + base, B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys, (uint32_t)nl, &ls};
+      return run_row32(p.logc, b.kind, ROW_MUL, ra, s);
+    }
+    uint32_t* wb = same ? c + base : ws + base;
+    ColArgsT<uint32_t> cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
+                          same ? 1u : 2u, &ls};
+    hipError_t e = run_col32(p.logr, b.kind, false, cf, s);
+    if (e != hipSuccess) return e;
+    RowArgsT<uint32_t> ra{c + base, wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl, &ls};
+    if ((e = run_row32(p.logc, b.kind, ROW_MUL, ra, s)) != hipSuccess) return e;
+    ColArgsT<uint32_t> ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1,
+                          &ls};
+    return run_col32(p.logr, b.kind, true, ci, s);
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
+}
+
+// ------------------------------------------------------ interleaved layout --
+// Batch [limb][N][polys]: coefficient j of polynomial p at j * polys + p.
+// A transform is a sequence of radix-2^r blocks of stages (il_kernels.hip),
+// each one launch over the whole batch; n stages split into the fewest
+// blocks of at most IL_MAXR stages, balanced, larger blocks first; the fused
+// middle block of the product holds two operands and takes at most
+// IL_MUL_MAXR stages.
+
+static int il_plan(unsigned n, int maxlast, int* sizes) {
+  int np = (int)((n + IL_MAXR - 1) / IL_MAXR);
+  for (;; ++np) {
+    const int base = (int)n / np, rem = (int)n % np;
+    for (int i = 0; i < np; ++i) sizes[i] = base + (i < rem ? 1 : 0);
+    if (sizes[np - 1] <= maxlast) return np;
+  }
+}
+
+static const char* il_name(int mode, int logr) {
+  static std::vector<std::string> names = [] {
+    std::vector<std::string> v;
+    const char* m[3] = {"il_fwd_r", "il_inv_r", "il_mul_r"};
+    for (int i = 0; i < 3; ++i)
+      for (int r = 0; r <= IL_MAXR; ++r) v.push_back(std::string(m[i]) + std::to_string(r));
+    return v;
+  }();
+  return names[mode * (IL_MAXR + 1) + logr].c_str();
+}
+
+static hipError_t run_il(int logr, int kind, int mode, const IlArgs& a, hipStream_t s) {
+  ProfScope ps(s, il_name(mode, logr));
+  return launch_il(logr, kind, mode, a, s);
+}
+
+static int ntt_common_il(uint64_t* x, size_t N, size_t limbs, size_t polys, const uint64_t* q,
+                         const uint64_t* tw, pm_stream_t stream, bool inv) {
+  Batch b;
+  int rc;
+  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr(x, "x")) || (rc = check_ptr(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
+  int sz[32];
+  const int np = il_plan(b.log2n, IL_MAXR, sz);
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
+    uint64_t* xs = x + l0 * polys * N;
+    const uint64_t* t = tw + l0 * N;
+    IlArgs a{xs, nullptr, xs, nullptr, t, t, b.log2n, 0, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+    hipError_t e;
+    if (!inv) {
+      for (int k = 0; k < np; ++k) {
+        if ((e = run_il(sz[k], b.kind, IL_FWD, a, s)) != hipSuccess) return e;
+        a.s0 += (uint32_t)sz[k];
+      }
+    } else {
+      a.s0 = b.log2n;
+      for (int k = np - 1; k >= 0; --k) {
+        a.s0 -= (uint32_t)sz[k];
+        if ((e = run_il(sz[k], b.kind, IL_INV, a, s)) != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
+}
+
+int pm_ntt_fwd_il(uint64_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t* q,
+                  const uint64_t* psi_br, pm_stream_t stream) {
+  return ntt_common_il(x, N, limbs, polys_per_limb, q, psi_br, stream, false);
+}
+
+int pm_ntt_inv_il(uint64_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t* q,
+                  const uint64_t* psi_inv_br, pm_stream_t stream) {
+  return ntt_common_il(x, N, limbs, polys_per_limb, q, psi_inv_br, stream, true);
+}
+
+size_t pm_polymul_il_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {
+  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N)) return 0;
+  int sz[32];
+  return il_plan(log2u(N), IL_MUL_MAXR, sz) > 1 ? N * limbs * polys_per_limb * sizeof(uint64_t) : 0;
+}
+
+int pm_polymul_il(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, size_t limbs,
+                  size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br, const uint64_t* psi_inv_br,
+                  void* workspace, pm_stream_t stream) {
+  Batch b;
+  int rc;
+  const size_t polys = polys_per_limb;
+  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr(a, "a")) || (rc = check_ptr(b_, "b")) || (rc = check_ptr(c, "c")) ||
+      (rc = check_ptr(psi_br, "psi_br")) || (rc = check_ptr(psi_inv_br, "psi_inv_br")))
+    return rc;
+  int sz[32];
+  const int np = il_plan(b.log2n, IL_MUL_MAXR, sz);
+  const bool same = (a == b_);
+  const uint64_t* A = a;
+  const uint64_t* B = b_;
+  if (c == B && c != A) std::swap(A, B);
+  if (np > 1 && !same && (rc = check_ptr(workspace, "workspace"))) return rc;
+  uint64_t* ws = (uint64_t*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
+    const size_t base = l0 * polys * N;
+    const uint64_t* tf = psi_br + l0 * N;
+    const uint64_t* ti = psi_inv_br + l0 * N;
+    hipError_t e;
+    if (np == 1) {
+      IlArgs m{A + base, B + base, c + base, nullptr, tf, ti, b.log2n, 0, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+      return run_il(sz[0], b.kind, IL_MUL, m, s);
+    }
+    uint64_t* wb = same ? c + base : ws + base;
+    // forward blocks of a (-> c) and b (-> workspace), then in place
+    IlArgs f{A + base, B + base, c + base, wb, tf, ti, b.log2n, 0, (uint32_t)polys, (uint32_t)nl,
+             same ? 1u : 2u, &ls};
+    for (int k = 0; k < np - 1; ++k) {
+      if ((e = run_il(sz[k], b.kind, IL_FWD, f, s)) != hipSuccess) return e;
+      f.A = c + base;
+      f.B = wb;
+      f.s0 += (uint32_t)sz[k];
+    }
+    IlArgs m{c + base, wb, c + base, nullptr, tf, ti, b.log2n, f.s0, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+    if ((e = run_il(sz[np - 1], b.kind, IL_MUL, m, s)) != hipSuccess) return e;
+    IlArgs iv{c + base, nullptr, c + base, nullptr, tf, ti, b.log2n, f.s0, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+    for (int k = np - 2; k >= 0; --k) {
+      iv.s0 -= (uint32_t)sz[k];
+      if ((e = run_il(sz[k], b.kind, IL_INV, iv, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
+}
+
 // ------------------------------------------------------------ host helpers --
 
 static uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
@@ -412,6 +734,19 @@ int pm_make_tables(uint64_t q, size_t N, uint64_t psi, uint64_t* psi_br, uint64_
     psi_inv_br[i] = pwi[r];
   }
   g_err.clear();
+  return PM_OK;
+}
+
+int pm_make_tables_u32(uint32_t q, size_t N, uint32_t psi, uint32_t* psi_br, uint32_t* psi_inv_br) {
+  if ((q >> 30) != 0 || !psi_br || !psi_inv_br) return fail(PM_EINVAL, "bad arguments (q must be below 2^30)");
+  if (!is_pow2(N)) return fail(PM_EINVAL, "bad arguments");
+  std::vector<uint64_t> f(N), i(N);
+  int rc = pm_make_tables(q, N, psi, f.data(), i.data());
+  if (rc) return rc;
+  for (size_t k = 0; k < N; ++k) {
+    psi_br[k] = (uint32_t)f[k];
+    psi_inv_br[k] = (uint32_t)i[k];
+  }
   return PM_OK;
 }
 

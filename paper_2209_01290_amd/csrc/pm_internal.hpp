@@ -5,46 +5,80 @@
 #include <stddef.h>
 
 #include "modarith.hpp"
+#include "modarith32.hpp"
 
 namespace pm {
 
 // Moduli of up to MAXL limbs travel by value in the kernel arguments; larger
-// batches are launched in chunks of MAXL limbs.
+// batches are launched in chunks of MAXL limbs. Word types: uint64_t (q < 2^62,
+// constants in Mod) and uint32_t (q < 2^30, constants in Mod32).
 constexpr int MAXL = 64;
-struct LimbSet {
-  Mod mod[MAXL];
+
+template <typename W> struct ModOf { using type = Mod; };
+template <> struct ModOf<uint32_t> { using type = Mod32; };
+
+template <typename W>
+struct LimbSetT {
+  typename ModOf<W>::type mod[MAXL];
 };
+using LimbSet = LimbSetT<uint64_t>;
+using LimbSet32 = LimbSetT<uint32_t>;
 
 enum { ROW_FWD = 0, ROW_INV = 1, ROW_MUL = 2, ROW_SQR = 3, ROW_FMUL = 4 };
 
-struct RowArgs {
-  const uint64_t* A;      // input rows (FWD/INV: in place with C allowed)
-  const uint64_t* B;      // second operand (MUL only)
-  uint64_t* C;            // output rows
-  const uint64_t* twf;    // psi_br, [limbs][N]
-  const uint64_t* twi;    // psi_inv_br, [limbs][N]
+template <typename W>
+struct RowArgsT {
+  const W* A;             // input rows (FWD/INV: in place with C allowed)
+  const W* B;             // second operand (MUL only)
+  W* C;                   // output rows
+  const W* twf;           // psi_br, [limbs][N]
+  const W* twi;           // psi_inv_br, [limbs][N]
   uint32_t log2n, R, polys, limbs;
-  const LimbSet* ls;
+  const LimbSetT<W>* ls;
 };
+using RowArgs = RowArgsT<uint64_t>;
 
-struct ColArgs {
-  const uint64_t* src0;
-  uint64_t* dst0;
-  const uint64_t* src1;   // second operand (nops == 2)
-  uint64_t* dst1;
-  const uint64_t* tw;     // [limbs][N]
+template <typename W>
+struct ColArgsT {
+  const W* src0;
+  W* dst0;
+  const W* src1;          // second operand (nops == 2)
+  W* dst1;
+  const W* tw;            // [limbs][N]
   uint32_t log2n, polys, limbs, nops;
-  const LimbSet* ls;
+  const LimbSetT<W>* ls;
 };
+using ColArgs = ColArgsT<uint64_t>;
 
 hipError_t launch_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t n, const Mod& M, int kind,
                          hipStream_t s);
 hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s);
-#define PM_DECL_ROW(L) hipError_t launch_row_##L(int kind, int mode, const RowArgs& a, hipStream_t s);
+hipError_t launch_row(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s);
+#define PM_DECL_ROW(L)                                                                        \
+  hipError_t launch_row_##L(int kind, int mode, const RowArgs& a, hipStream_t s);             \
+  hipError_t launch_row_##L(int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s);
 PM_DECL_ROW(1) PM_DECL_ROW(2) PM_DECL_ROW(3) PM_DECL_ROW(4) PM_DECL_ROW(5) PM_DECL_ROW(6) PM_DECL_ROW(7)
 PM_DECL_ROW(8) PM_DECL_ROW(9) PM_DECL_ROW(10) PM_DECL_ROW(11) PM_DECL_ROW(12) PM_DECL_ROW(13) PM_DECL_ROW(14)
 #undef PM_DECL_ROW
 hipError_t launch_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_t s);
+hipError_t launch_col(int logr, int kind, bool inv, const ColArgsT<uint32_t>& a, hipStream_t s);
+
+// Interleaved (coefficient-major) layout: one radix-2^logr block of stages
+// s0..s0+logr-1 per launch (il_kernels.hip).
+enum { IL_FWD = 0, IL_INV = 1, IL_MUL = 2 };
+constexpr int IL_MAXR = 6;       // words per thread: 2^6 (128 VGPRs of data)
+constexpr int IL_MUL_MAXR = 5;   // the fused block holds both operands' words
+struct IlArgs {
+  const uint64_t* A;
+  const uint64_t* B;             // second operand (IL_FWD with nops == 2, IL_MUL)
+  uint64_t* C;
+  uint64_t* D;                   // second output (IL_FWD with nops == 2)
+  const uint64_t* twf;           // psi_br, [limbs][N]
+  const uint64_t* twi;           // psi_inv_br, [limbs][N]
+  uint32_t log2n, s0, polys, limbs, nops;
+  const LimbSet* ls;
+};
+hipError_t launch_il(int logr, int kind, int mode, const IlArgs& a, hipStream_t s);
 hipError_t launch_stage(int kind, bool inv, const ColArgs& a, uint32_t log2m, hipStream_t s);
 hipError_t launch_pointwise(int kind, const uint64_t* A, const uint64_t* B, uint64_t* C, uint32_t log2n,
                             uint32_t polys, uint32_t limbs, const LimbSet& ls, hipStream_t s);

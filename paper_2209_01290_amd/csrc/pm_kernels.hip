@@ -26,21 +26,21 @@ __global__ void __launch_bounds__(256) k_mulmod(const uint64_t* __restrict__ a, 
 
 // ---------------------------------------------------------------- column --
 // grid: x = block of 256 columns, y = poly, z = limb * nops + op.
-template <int LOGR, int KIND, int INV>
+template <int LOGR, int KIND, int INV, typename W>
 __global__ void __launch_bounds__(256)
-k_col(const uint64_t* src0, uint64_t* dst0, const uint64_t* src1, uint64_t* dst1,
-      const uint64_t* __restrict__ tw, uint32_t log2n, uint32_t polys, uint32_t nops, LimbSet ls) {
+k_col(const W* src0, W* dst0, const W* src1, W* dst1, const W* __restrict__ tw, uint32_t log2n, uint32_t polys,
+      uint32_t nops, LimbSetT<W> ls) {
   constexpr int R = 1 << LOGR;
   const uint32_t limb = blockIdx.z / nops, op = blockIdx.z - limb * nops;
   const uint32_t poly = blockIdx.y;
   const size_t N = (size_t)1 << log2n, C = N >> LOGR;
   const size_t col = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t off = ((size_t)limb * polys + poly) * N + col;
-  const uint64_t* src = (op ? src1 : src0) + off;
-  uint64_t* dst = (op ? dst1 : dst0) + off;
-  const uint64_t* t = tw + (size_t)limb * N;
-  const Mod M = ls.mod[limb];
-  uint64_t x[R];
+  const W* src = (op ? src1 : src0) + off;
+  W* dst = (op ? dst1 : dst0) + off;
+  const W* t = tw + (size_t)limb * N;
+  const typename ModOf<W>::type M = ls.mod[limb];
+  W x[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) x[i] = src[i * C];
   if (INV) col_inv<LOGR, KIND>(x, t, M);
@@ -100,7 +100,8 @@ hipError_t launch_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size
   return hipGetLastError();
 }
 
-hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s) {
+template <typename A>
+static hipError_t launch_row_any(int logc, int kind, int mode, const A& a, hipStream_t s) {
   switch (logc) {
 #define PM_ROW_CASE(L) case L: return launch_row_##L(kind, mode, a, s);
     PM_ROW_CASE(1) PM_ROW_CASE(2) PM_ROW_CASE(3) PM_ROW_CASE(4) PM_ROW_CASE(5) PM_ROW_CASE(6)
@@ -111,25 +112,34 @@ hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_
   }
 }
 
-template <int LOGR, int KIND>
-static void col_launch(const ColArgs& a, bool inv, hipStream_t s) {
+hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s) {
+  return launch_row_any(logc, kind, mode, a, s);
+}
+
+hipError_t launch_row(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s) {
+  return launch_row_any(logc, kind, mode, a, s);
+}
+
+template <int LOGR, int KIND, typename W>
+static void col_launch(const ColArgsT<W>& a, bool inv, hipStream_t s) {
   const size_t C = ((size_t)1 << a.log2n) >> LOGR;
   dim3 grid((uint32_t)(C / 256), a.polys, a.limbs * a.nops);
   if (inv)
-    hipLaunchKernelGGL((k_col<LOGR, KIND, 1>), grid, dim3(256), 0, s, a.src0, a.dst0, a.src1, a.dst1, a.tw,
+    hipLaunchKernelGGL((k_col<LOGR, KIND, 1, W>), grid, dim3(256), 0, s, a.src0, a.dst0, a.src1, a.dst1, a.tw,
                        a.log2n, a.polys, a.nops, *a.ls);
   else
-    hipLaunchKernelGGL((k_col<LOGR, KIND, 0>), grid, dim3(256), 0, s, a.src0, a.dst0, a.src1, a.dst1, a.tw,
+    hipLaunchKernelGGL((k_col<LOGR, KIND, 0, W>), grid, dim3(256), 0, s, a.src0, a.dst0, a.src1, a.dst1, a.tw,
                        a.log2n, a.polys, a.nops, *a.ls);
 }
 
-template <int LOGR>
-static void col_launch_kind(const ColArgs& a, int kind, bool inv, hipStream_t s) {
+template <int LOGR, typename W>
+static void col_launch_kind(const ColArgsT<W>& a, int kind, bool inv, hipStream_t s) {
   if (kind == KIND_WIDE) col_launch<LOGR, KIND_WIDE>(a, inv, s);
   else col_launch<LOGR, KIND_ANY>(a, inv, s);
 }
 
-hipError_t launch_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_t s) {
+template <typename W>
+static hipError_t launch_col_any(int logr, int kind, bool inv, const ColArgsT<W>& a, hipStream_t s) {
   switch (logr) {
     case 1: col_launch_kind<1>(a, kind, inv, s); break;
     case 2: col_launch_kind<2>(a, kind, inv, s); break;
@@ -139,6 +149,14 @@ hipError_t launch_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_t s) {
+  return launch_col_any(logr, kind, inv, a, s);
+}
+
+hipError_t launch_col(int logr, int kind, bool inv, const ColArgsT<uint32_t>& a, hipStream_t s) {
+  return launch_col_any(logr, kind, inv, a, s);
 }
 
 hipError_t launch_stage(int kind, bool inv, const ColArgs& a, uint32_t log2m, hipStream_t s) {

@@ -56,6 +56,7 @@ def load():
         lib = ctypes.CDLL(LIB_PATH)
         vp, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
         u64p = ctypes.POINTER(ctypes.c_uint64)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
         sig = {
             "pm_last_error": (ctypes.c_char_p, []),
             "pm_barrett_mulmod": (i32, [vp, vp, vp, sz, u64, vp]),
@@ -81,6 +82,15 @@ def load():
             "pm_reduce_apply": (i32, [i32, ctypes.c_uint, vp, vp, vp, vp, sz, u64, vp]),
             "pm_reduce_chain": (i32, [i32, ctypes.c_uint, vp, sz, u64, i32, u64, vp]),
             "pm_prof_read": (i32, [ctypes.POINTER(ProfEntry), sz, ctypes.POINTER(sz), i32]),
+            "pm_ntt_fwd_il": (i32, [vp, sz, sz, sz, u64p, vp, vp]),
+            "pm_ntt_inv_il": (i32, [vp, sz, sz, sz, u64p, vp, vp]),
+            "pm_polymul_il": (i32, [vp, vp, vp, sz, sz, sz, u64p, vp, vp, vp, vp]),
+            "pm_polymul_il_workspace_bytes": (sz, [sz, sz, sz]),
+            "pm_ntt_fwd_u32": (i32, [vp, sz, sz, sz, u32p, vp, vp]),
+            "pm_ntt_inv_u32": (i32, [vp, sz, sz, sz, u32p, vp, vp]),
+            "pm_polymul_u32": (i32, [vp, vp, vp, sz, sz, sz, u32p, vp, vp, vp, vp]),
+            "pm_polymul_u32_workspace_bytes": (sz, [sz, sz, sz]),
+            "pm_make_tables_u32": (i32, [ctypes.c_uint32, sz, ctypes.c_uint32, u32p, u32p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -97,7 +107,10 @@ def exported_symbols():
             "pm_polymul_stagewise_workspace_bytes", "pm_tune_set", "pm_tune_get",
             "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read",
             "pm_polymul_jobs_workspace_bytes", "pm_polymul_jobs", "pm_plan_create", "pm_plan_launch",
-            "pm_plan_destroy", "pm_plan_device_bytes", "pm_reduce_apply", "pm_reduce_chain"]
+            "pm_plan_destroy", "pm_plan_device_bytes", "pm_reduce_apply", "pm_reduce_chain",
+            "pm_ntt_fwd_u32", "pm_ntt_inv_u32", "pm_polymul_u32", "pm_polymul_u32_workspace_bytes",
+            "pm_make_tables_u32", "pm_ntt_fwd_il", "pm_ntt_inv_il", "pm_polymul_il",
+            "pm_polymul_il_workspace_bytes"]
 
 
 def _check(rc: int, func: str):
@@ -121,6 +134,32 @@ def _dptr(t, name):
     return t.data_ptr()
 
 
+def _dptr32(t, name):
+    """Device pointer of a contiguous 32-bit integer tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live on a HIP device" % name)
+    if t.element_size() != 4 or t.dtype.is_floating_point:
+        raise TypeError("%s must be int32 or uint32" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def _wptr(t):
+    """Device pointer of a workspace tensor of any integer type (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("workspace must be a contiguous tensor on a HIP device")
+    return t.data_ptr()
+
+
 def _stream(stream, like=None):
     import torch
     if stream is None:
@@ -136,6 +175,15 @@ def _qarr(q, limbs):
     if len(qs) != limbs:
         raise ValueError("need %d moduli, got %d" % (limbs, len(qs)))
     return (ctypes.c_uint64 * limbs)(*qs)
+
+
+def _qarr32(q, limbs):
+    qs = [int(x) for x in (q if hasattr(q, "__len__") else [q])]
+    if len(qs) != limbs:
+        raise ValueError("need %d moduli, got %d" % (limbs, len(qs)))
+    if any(x < 0 or x >= 1 << 32 for x in qs):
+        raise ValueError("32-bit moduli expected")
+    return (ctypes.c_uint32 * limbs)(*qs)
 
 
 # ------------------------------------------------------------ entry points --
@@ -182,6 +230,47 @@ def pm_polymul_stagewise(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_b
                                        polys_per_limb, _qarr(q, limbs), _dptr(psi_br, "psi_br"),
                                        _dptr(psi_inv_br, "psi_inv_br"), _dptr(workspace, "workspace"),
                                        _stream(stream, a)), "pm_polymul_stagewise")
+
+
+def pm_ntt_fwd_il(x, N, limbs, polys_per_limb, q, psi_br, stream=None):
+    """Forward transform of a coefficient-major batch x[limb][N][polys_per_limb]."""
+    _check(load().pm_ntt_fwd_il(_dptr(x, "x"), N, limbs, polys_per_limb, _qarr(q, limbs),
+                                _dptr(psi_br, "psi_br"), _stream(stream, x)), "pm_ntt_fwd_il")
+
+
+def pm_ntt_inv_il(x, N, limbs, polys_per_limb, q, psi_inv_br, stream=None):
+    _check(load().pm_ntt_inv_il(_dptr(x, "x"), N, limbs, polys_per_limb, _qarr(q, limbs),
+                                _dptr(psi_inv_br, "psi_inv_br"), _stream(stream, x)), "pm_ntt_inv_il")
+
+
+def pm_polymul_il_workspace_bytes(N, limbs, polys_per_limb):
+    return int(load().pm_polymul_il_workspace_bytes(N, limbs, polys_per_limb))
+
+
+def pm_polymul_il(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace=None, stream=None):
+    _check(load().pm_polymul_il(_dptr(a, "a"), _dptr(b, "b"), _dptr(c, "c"), N, limbs, polys_per_limb,
+                                _qarr(q, limbs), _dptr(psi_br, "psi_br"), _dptr(psi_inv_br, "psi_inv_br"),
+                                _wptr(workspace), _stream(stream, a)), "pm_polymul_il")
+
+
+def pm_ntt_fwd_u32(x, N, limbs, polys_per_limb, q, psi_br, stream=None):
+    _check(load().pm_ntt_fwd_u32(_dptr32(x, "x"), N, limbs, polys_per_limb, _qarr32(q, limbs),
+                                 _dptr32(psi_br, "psi_br"), _stream(stream, x)), "pm_ntt_fwd_u32")
+
+
+def pm_ntt_inv_u32(x, N, limbs, polys_per_limb, q, psi_inv_br, stream=None):
+    _check(load().pm_ntt_inv_u32(_dptr32(x, "x"), N, limbs, polys_per_limb, _qarr32(q, limbs),
+                                 _dptr32(psi_inv_br, "psi_inv_br"), _stream(stream, x)), "pm_ntt_inv_u32")
+
+
+def pm_polymul_u32_workspace_bytes(N, limbs, polys_per_limb):
+    return int(load().pm_polymul_u32_workspace_bytes(N, limbs, polys_per_limb))
+
+
+def pm_polymul_u32(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace=None, stream=None):
+    _check(load().pm_polymul_u32(_dptr32(a, "a"), _dptr32(b, "b"), _dptr32(c, "c"), N, limbs, polys_per_limb,
+                                 _qarr32(q, limbs), _dptr32(psi_br, "psi_br"), _dptr32(psi_inv_br, "psi_inv_br"),
+                                 _wptr(workspace), _stream(stream, a)), "pm_polymul_u32")
 
 
 PM_PLAN_NO_GRAPH = 1
@@ -324,6 +413,18 @@ def pm_make_tables(q, N, psi=None):
     return fwd, inv
 
 
+def pm_make_tables_u32(q, N, psi=None):
+    """(psi_br, psi_inv_br) as numpy uint32 arrays of N words (q < 2^30)."""
+    if psi is None:
+        psi = pm_find_psi(q, N)
+    fwd = np.empty(N, dtype=np.uint32)
+    inv = np.empty(N, dtype=np.uint32)
+    p = ctypes.POINTER(ctypes.c_uint32)
+    _check(load().pm_make_tables_u32(q, N, psi, fwd.ctypes.data_as(p), inv.ctypes.data_as(p)),
+           "pm_make_tables_u32")
+    return fwd, inv
+
+
 # ------------------------------------------------------------- helpers ----
 
 def to_device(arr: np.ndarray, device="cuda"):
@@ -335,6 +436,17 @@ def to_device(arr: np.ndarray, device="cuda"):
 def to_host(t) -> np.ndarray:
     """torch 64-bit tensor -> numpy uint64 (same bits)."""
     return t.detach().to("cpu").contiguous().numpy().view(np.uint64)
+
+
+def to_device32(arr: np.ndarray, device="cuda"):
+    """numpy array of values < 2^31 -> torch int32 tensor on the device."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.uint32).view(np.int32)).to(device)
+
+
+def to_host32(t) -> np.ndarray:
+    """torch 32-bit tensor -> numpy uint32 (same bits)."""
+    return t.detach().to("cpu").contiguous().numpy().view(np.uint32)
 
 
 class Params:
@@ -355,3 +467,23 @@ class Params:
         self.psi_br_host, self.psi_inv_br_host = fw, iv
         self.psi_br = to_device(fw, device)
         self.psi_inv_br = to_device(iv, device)
+
+
+class Params32:
+    """Moduli (< 2^30) and device-resident 32-bit twiddle tables for `limbs`
+    limbs of size N: the l-th largest prime q < 2^bits with q = 1 mod 2N."""
+
+    def __init__(self, N, limbs, bits=30, device="cuda", primes=None):
+        if bits > 30:
+            raise ValueError("32-bit words take moduli of at most 30 bits")
+        self.N, self.limbs = N, limbs
+        self.q = list(primes) if primes is not None else pm_ntt_primes(N, limbs, bits)
+        if len(self.q) != limbs:
+            raise ValueError("not enough primes")
+        fw = np.empty((limbs, N), dtype=np.uint32)
+        iv = np.empty((limbs, N), dtype=np.uint32)
+        for l, q in enumerate(self.q):
+            fw[l], iv[l] = pm_make_tables_u32(q, N)
+        self.psi_br_host, self.psi_inv_br_host = fw, iv
+        self.psi_br = to_device32(fw, device)
+        self.psi_inv_br = to_device32(iv, device)

@@ -122,3 +122,58 @@ def test_tune_db_applies(L, tmp_path):
     finally:
         L.pm_tune_set(L.OP_POLYMUL, 15, 0)
         L.pm_tune_set(L.OP_NTT_FWD, 13, 0)
+
+
+def test_u32_invalid_arguments_rejected_on_host(L):
+    lib = L.load()
+    q30 = L.pm_ntt_primes(1024, 1, 30)[0]
+    q = (ctypes.c_uint32 * 1)(q30)
+    for N in [0, 1, 3, 1 << 18]:
+        assert lib.pm_polymul_u32(FAKE, FAKE, FAKE, N, 1, 1, q, FAKE, FAKE, FAKE, None) == L.PM_EINVAL
+        assert lib.pm_ntt_fwd_u32(FAKE, N, 1, 1, q, FAKE, None) == L.PM_EINVAL
+    # a 31-bit modulus (Alg. 4 on 32-bit words needs len(q) <= 30), even q, 2N not dividing q-1
+    q31 = L.pm_ntt_primes(1024, 1, 31)[0]
+    for bad in [q31, q30 - 1, q30 + 2]:
+        qb = (ctypes.c_uint32 * 1)(bad)
+        assert lib.pm_polymul_u32(FAKE, FAKE, FAKE, 1024, 1, 1, qb, FAKE, FAKE, FAKE, None) == L.PM_EINVAL
+        assert lib.pm_ntt_inv_u32(FAKE, 1024, 1, 1, qb, FAKE, None) == L.PM_EINVAL
+    # 4-byte alignment suffices for 32-bit words; 2-byte does not
+    assert lib.pm_polymul_u32(ctypes.c_void_p(0x10002), FAKE, FAKE, 1024, 1, 1, q, FAKE, FAKE, FAKE,
+                              None) == L.PM_EINVAL
+    assert "aligned" in lib.pm_last_error().decode()
+    # a 2-D split needs the workspace
+    q16 = (ctypes.c_uint32 * 1)(L.pm_ntt_primes(1 << 16, 1, 30)[0])
+    assert lib.pm_polymul_u32(FAKE, ctypes.c_void_p(0x20000), FAKE, 1 << 16, 1, 1, q16, FAKE, FAKE, None,
+                              None) == L.PM_EINVAL
+    assert "workspace" in lib.pm_last_error().decode()
+    assert L.pm_polymul_u32_workspace_bytes(1 << 16, 4, 2) == (1 << 16) * 4 * 2 * 4
+    assert L.pm_polymul_u32_workspace_bytes(1024, 4, 2) == 0
+
+
+@pytest.mark.parametrize("N,bits", [(1024, 30), (1 << 14, 29), (1 << 16, 28)])
+def test_u32_tables_match_oracle(L, N, bits):
+    o = oracle.default()
+    q = L.pm_ntt_primes(N, 1, bits)[0]
+    assert q < 1 << bits and q == o.ntt_primes(N, 1, bits)[0]
+    f, i = L.pm_make_tables_u32(q, N)
+    assert f.dtype == np.uint32
+    if N <= 1 << 14:
+        f2, i2 = o.psi_tables(q, N)
+        assert np.array_equal(f.astype(np.uint64), f2) and np.array_equal(i.astype(np.uint64), i2)
+    with pytest.raises(L.PMError):
+        L.pm_make_tables_u32(L.pm_ntt_primes(N, 1, 31)[0], N)
+
+
+def test_il_invalid_arguments_and_workspace(L):
+    lib = L.load()
+    q = (ctypes.c_uint64 * 1)(0x0FFFFFFFFFFFC001)
+    for N in [0, 3, 1 << 18]:
+        assert lib.pm_polymul_il(FAKE, FAKE, FAKE, N, 1, 1, q, FAKE, FAKE, FAKE, None) == L.PM_EINVAL
+        assert lib.pm_ntt_fwd_il(FAKE, N, 1, 1, q, FAKE, None) == L.PM_EINVAL
+    assert lib.pm_ntt_inv_il(FAKE, 1024, 1, 0, q, FAKE, None) == L.PM_EINVAL
+    # up to 2^5 stages run as one fused block: no workspace below N = 64
+    assert L.pm_polymul_il_workspace_bytes(32, 3, 7) == 0
+    assert L.pm_polymul_il_workspace_bytes(64, 3, 7) == 64 * 3 * 7 * 8
+    assert lib.pm_polymul_il(FAKE, ctypes.c_void_p(0x20000), FAKE, 1024, 1, 1, q, FAKE, FAKE, None,
+                             None) == L.PM_EINVAL
+    assert "workspace" in lib.pm_last_error().decode()
