@@ -1,0 +1,119 @@
+"""Weak-scaling study of the transforms on one GPU (Sec. V-C and the
+single-block scaling experiment of Sec. VI), in both batch layouts:
+
+  * batch scaling (the throughput-optimised multi-block design): forward
+    NTTs of N = 2^16 under one 60-bit modulus, the batch doubled from 1 to
+    2^15 polynomials (the paper's largest shape: 2^15 transforms of 2^16
+    points), each batch one call; time per call and per transform, in the
+    [poly][N] layout (pm_ntt_fwd) and the coefficient-major [N][poly] layout
+    (pm_ntt_fwd_il);
+  * single-transform scaling: one forward NTT of N = 2^10 .. 2^17, where the
+    number of workgroups grows with N (the paper doubles N and the block
+    count together), median latency per call.
+
+Operands: uniform in [0, q) from the seeded device generator. Every timing is
+the median of HIP-event intervals between consecutive calls on one stream.
+
+Usage on a GPU:  python -m paper_2209_01290_amd.scaling [--max-log2p 15] [--out F]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+SEED = 220901290 + 9
+
+
+def _median_us(torch, fn, reps):
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        fn()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(reps):
+        fn()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    xs = sorted(ev[k].elapsed_time(ev[k + 1]) * 1e3 for k in range(reps))
+    return xs[len(xs) // 2]
+
+
+def batch_scaling(torch, lib, log2n=16, max_log2p=15, verbose=True):
+    from . import synth
+    dev = torch.device("cuda")
+    N = 1 << log2n
+    prm = lib.Params(N, 1, device=dev)
+    rows = []
+    for lp in range(0, max_log2p + 1):
+        P = 1 << lp
+        x = torch.empty(P * N, dtype=torch.int64, device=dev)
+        chunk = min(P * N, 1 << 24)          # drawn 2^24 words at a time (stream = chunk index)
+        for c in range(P * N // chunk):
+            synth.uniform_mod_device([synth.key(SEED, lp, c)], chunk, prm.q, x[c * chunk:(c + 1) * chunk].view(1, chunk))
+        reps = max(5, min(200, (1 << 22) // (P * N // 64 + 1)))
+        row = {"N": N, "polys": P, "bytes": P * N * 8}
+        for name, fn in (("standard", lambda: lib.pm_ntt_fwd(x, N, 1, P, prm.q, prm.psi_br)),
+                         ("interleaved", lambda: lib.pm_ntt_fwd_il(x, N, 1, P, prm.q, prm.psi_br))):
+            us = _median_us(torch, fn, reps)
+            row[name + "_us_per_call"] = round(us, 2)
+            row[name + "_us_per_ntt"] = round(us / P, 4)
+        rows.append(row)
+        if verbose:
+            print(json.dumps(row), flush=True)
+        del x
+        torch.cuda.empty_cache()
+    return rows
+
+
+def single_scaling(torch, lib, verbose=True):
+    from . import synth
+    dev = torch.device("cuda")
+    rows = []
+    for log2n in range(10, 18):
+        N = 1 << log2n
+        prm = lib.Params(N, 1, device=dev)
+        a, _ = synth.operands(SEED, prm.q, 1, N)
+        x = lib.to_device(a, dev)
+        row = {"N": N,
+               "ntt_us": round(_median_us(torch, lambda: lib.pm_ntt_fwd(x, N, 1, 1, prm.q, prm.psi_br), 200), 2),
+               "intt_us": round(_median_us(torch, lambda: lib.pm_ntt_inv(x, N, 1, 1, prm.q, prm.psi_inv_br),
+                                           200), 2)}
+        rows.append(row)
+        if verbose:
+            print(json.dumps(row), flush=True)
+    return rows
+
+
+def markdown(batch, single) -> str:
+    md = ["| N | polys | [poly][N]: us/call | us/NTT | [N][poly]: us/call | us/NTT |",
+          "|---|---|---|---|---|---|"]
+    for r in batch:
+        md.append("| 2^%d | %d | %.1f | %.4f | %.1f | %.4f |" % (
+            r["N"].bit_length() - 1, r["polys"], r["standard_us_per_call"], r["standard_us_per_ntt"],
+            r["interleaved_us_per_call"], r["interleaved_us_per_ntt"]))
+    md += ["", "| N | one NTT (us) | one iNTT (us) |", "|---|---|---|"]
+    for r in single:
+        md.append("| 2^%d | %.2f | %.2f |" % (r["N"].bit_length() - 1, r["ntt_us"], r["intt_us"]))
+    return "\n".join(md) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--max-log2p", type=int, default=15)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    import torch
+    from . import lib
+    lib.load()
+    lib.apply_tune_db()
+    single = single_scaling(torch, lib)
+    batch = batch_scaling(torch, lib, max_log2p=a.max_log2p)
+    print(markdown(batch, single), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump({"batch": batch, "single": single}, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
