@@ -47,26 +47,34 @@ PEAK_HBM_GBPS = 8000.0
 OPS_CT, OPS_GS, OPS_MUL = 37, 49, 25
 
 
-def alg_ops(name: str, N: int, limbs: int, polys: int) -> float:
-    """Algorithmic VALU lane-ops one launch of kernel `name` performs."""
-    if name.startswith("row_"):
-        logc = int(name.split("_c")[1])
-        C = 1 << logc
+# The same counts for 32-bit words (modarith32.hpp), moduli with m <= 29 /
+# m = 30 (one more shift per modular product).
+OPS32 = {29: (14, 21, 7), 30: (15, 22, 8)}
+
+
+def alg_ops(name: str, N: int, limbs: int, polys: int, ops=(OPS_CT, OPS_GS, OPS_MUL)) -> float:
+    """Algorithmic VALU lane-ops one launch of kernel `name` performs
+    (row_* / row32_*: fused row pass; col_* / col32_*: column pass)."""
+    ct, gs, mul = ops
+    kind, _, rest = name.partition("_")
+    if kind in ("row", "row32"):
+        mode, logc = rest.split("_c")
+        C = 1 << int(logc)
         rows = limbs * polys * (N // C)
-        half = (C // 2) * logc                 # butterflies of one row transform
-        if name.startswith("row_mul"):
-            per = 2 * half * OPS_CT + C * OPS_MUL + half * OPS_GS
-        elif name.startswith("row_fwd"):
-            per = half * OPS_CT
+        half = (C // 2) * int(logc)            # butterflies of one row transform
+        if mode == "mul":
+            per = 2 * half * ct + C * mul + half * gs
+        elif mode == "fwd":
+            per = half * ct
         else:
-            per = half * OPS_GS
+            per = half * gs
         return float(rows * per)
-    if name.startswith("col_"):
-        logr = int(name.split("_r")[1])
-        R = 1 << logr
+    if kind in ("col", "col32"):
+        mode, logr = rest.split("_r")
+        R = 1 << int(logr)
         cols = (N // R) * limbs * polys
-        nops = 2 if name.startswith("col_fwd") else 1
-        per = (R // 2) * logr * (OPS_CT if name.startswith("col_fwd") else OPS_GS)
+        nops = 2 if mode == "fwd" else 1
+        per = (R // 2) * int(logr) * (ct if mode == "fwd" else gs)
         return float(cols * nops * per)
     return float("nan")
 
@@ -212,10 +220,38 @@ def _median_call_us(torch, stream, fn, reps):
     return pct([ev[k].elapsed_time(ev[k + 1]) * 1e3 for k in range(reps)], 50)
 
 
+def _graph_call_us(torch, fn, calls=20, reps=10):
+    """Device time of one call without host overhead: `calls` consecutive calls
+    captured in one HIP graph, the graph replayed `reps` times; median per call."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(calls):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for k in range(reps):
+        g.replay()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) * 1e3 / calls for k in range(reps))
+    del g
+    return per[len(per) // 2]
+
+
 def words32(torch, lib, dev, steps=20):
     """The 32-bit word path (moduli up to 30 bits, Alg. 4 with beta = 32):
     single-transform latency at N = 2^14 and 2^16 beside 62-bit moduli on
-    64-bit words (the rows of the paper's comparison table in Sec. VII), and the workload-size
+    64-bit words (the rows of the paper's comparison table in Sec. VII; device
+    time per call from HIP-graph replays, and the time per call when each is
+    launched from Python), and the workload-size
     trade-off: the 2880-bit modulus of the headline workload as 96 30-bit
     limbs on 32-bit words against 48 60-bit limbs on 64-bit words."""
     from paper_2209_01290_amd import synth
@@ -237,8 +273,9 @@ def words32(torch, lib, dev, steps=20):
                 fwd = lambda: lib.pm_ntt_fwd(x, N, 1, 1, prm.q, prm.psi_br)
                 inv = lambda: lib.pm_ntt_inv(x, N, 1, 1, prm.q, prm.psi_inv_br)
             lat.append({"N": N, "q_bits": bits, "word_bits": 32 if bits <= 30 else 64,
-                        "ntt_us": round(_median_call_us(torch, stream, fwd, 200), 2),
-                        "intt_us": round(_median_call_us(torch, stream, inv, 200), 2)})
+                        "ntt_us": round(_graph_call_us(torch, fwd), 2),
+                        "intt_us": round(_graph_call_us(torch, inv), 2),
+                        "ntt_us_host_call": round(_median_call_us(torch, stream, fwd, 200), 2)})
     # same 2880-bit Q at N = 2^16, 8 pairs: 96 x 30-bit limbs on 32-bit words
     N, L32, P = 1 << 16, 96, POLYS
     prm = lib.Params32(N, L32, bits=30, device=dev)
@@ -264,6 +301,11 @@ def words32(torch, lib, dev, steps=20):
     lib.pm_prof_enable(False)
     k32 = lib.pm_prof_read(reset=True)
     ms = e0.elapsed_time(e1) / steps
+    dom = max(k32.items(), key=lambda kv: kv[1][1])[0]
+    _, dom_ms = k32[dom]
+    # algorithmic ops of one step: the moduli travel in chunks of 64 limbs per launch
+    ops = sum(alg_ops(dom, N, min(64, L32 - l0), P, OPS32[30]) for l0 in range(0, L32, 64))
+    achieved = ops * steps / (dom_ms / 1e3) / 1e12
     x = da.clone()
     ntt_us = _median_call_us(torch, stream, lambda: lib.pm_ntt_fwd_u32(x, N, L32, P, prm.q, prm.psi_br), 20)
     return {"what": "32-bit words, moduli < 2^30 (Alg. 4, beta = 32)",
@@ -273,7 +315,11 @@ def words32(torch, lib, dev, steps=20):
                 "limb_products_per_s": round(L32 * P / ms * 1e3, 1),
                 "q2880_products_per_s": round(P / ms * 1e3, 1),
                 "ntt_fwd_per_s": round(L32 * P / ntt_us * 1e6, 1),
-                "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(k32.items())}}}
+                "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(k32.items())},
+                "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+                             "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
+                             "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                             "ops_per_unit": {"ct": OPS32[30][0], "gs": OPS32[30][1], "mul": OPS32[30][2]}}}}
 
 
 def serving(lib, rates=(5000.0, 20000.0, 50000.0), nreq=4000):
