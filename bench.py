@@ -147,10 +147,26 @@ def cpu_baseline(N, qs, a_host, b_host, gpu_c, budget_s=12.0):
         l, p = pairs[k]
         if not np.array_equal(c, gpu_c[l, p]):
             raise SystemExit("GPU output differs from the oracle on limb %d pair %d" % (l, p))
+    # context for the one-product case: the O(N^2) schoolbook and the NTT
+    # route of the oracle for one N = 1024 product, one thread
+    from paper_2209_01290_amd import synth
+    q1 = 2 ** 60 - 2 ** 14 + 1
+    a1, b1 = synth.operands(220901290 + 1, [q1], 1, 1024)
+    t0 = time.perf_counter()
+    s1 = o.polymul_schoolbook(a1[0, 0], b1[0, 0], q1)
+    t_school = time.perf_counter() - t0
+    f1, i1 = o.psi_tables(q1, 1024)
+    t0 = time.perf_counter()
+    n1 = o.polymul_ntt(a1[0, 0], b1[0, 0], q1, f1, i1)
+    t_ntt = time.perf_counter() - t0
+    if not np.array_equal(s1, n1):
+        raise SystemExit("oracle schoolbook and NTT products differ at N=1024")
     return {"value": threads * reps / wall, "unit": "polymul/s", "cores": threads, "kind": "oracle",
             "sample": "%d products of the N=2^16 workload (%d per thread, %d threads, limbs %s), "
                       "textbook merged NTTs with %% reductions, gcc -O2; single-thread %.1f ms/product"
-                      % (threads * reps, reps, threads, sorted(set(l for l, _ in pairs)), 1e3 * t1)}
+                      % (threads * reps, reps, threads, sorted(set(l for l, _ in pairs)), 1e3 * t1),
+            "n1024_one_product_us": {"schoolbook": round(t_school * 1e6, 1), "ntt": round(t_ntt * 1e6, 1),
+                                     "threads": 1}}
 
 
 def mixed_batch(torch, lib, dev, launches=5):
@@ -320,6 +336,27 @@ def words32(torch, lib, dev, steps=20):
                              "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
                              "frac": round(achieved / PEAK_VALU_TOPS, 4),
                              "ops_per_unit": {"ct": OPS32[30][0], "gs": OPS32[30][1], "mul": OPS32[30][2]}}}}
+
+
+def single_polymul(torch, lib, dev):
+    """The latency-bound case: one product at N = 1024 under q = 2^60 - 2^14 + 1
+    (the largest 60-bit prime = 1 mod 2048), device time per call from HIP-graph
+    replays, with the installed small-batch plan and with the throughput plan."""
+    from paper_2209_01290_amd import synth
+    N = 1024
+    prm = lib.Params(N, 1, device=dev)
+    a, b = synth.operands(220901290 + 1, prm.q, 1, N)
+    da, db = lib.to_device(a, dev), lib.to_device(b, dev)
+    dc = torch.empty_like(da)
+    fn = lambda: lib.pm_polymul(da, db, dc, N, 1, 1, prm.q, prm.psi_br, prm.psi_inv_br, None)
+    out = {"what": "one N=1024 product, q = 2^60 - 2^14 + 1", "small_plan": lib.pm_tune_get_small(lib.OP_POLYMUL, 10),
+           "device_us": round(_graph_call_us(torch, fn), 2)}
+    keep = lib.pm_tune_get_small_batch()
+    lib.pm_tune_set_small_batch(0)
+    out["device_us_throughput_plan"] = round(_graph_call_us(torch, fn), 2)
+    lib.pm_tune_set_small_batch(keep)
+    out["host_call_us"] = round(_median_call_us(torch, torch.cuda.current_stream(dev), fn, 200), 2)
+    return out
 
 
 def serving(lib, rates=(5000.0, 20000.0, 50000.0), nreq=4000):
@@ -518,6 +555,7 @@ def main():
         step()
         torch.cuda.synchronize()
         out["mixed_batch"] = mixed_batch(torch, lib, dev)
+        out["single_polymul_n1024"] = single_polymul(torch, lib, dev)
         w32 = words32(torch, lib, dev)
         w32["polymul_96x30bit_limbs"]["vs_48x60bit_limbs_u64"] = round(
             w32["polymul_96x30bit_limbs"]["q2880_products_per_s"] / (value / LIMBS), 3)

@@ -232,6 +232,26 @@ int pm_reduce_chain(int variant, unsigned word_bits, uint64_t *out, size_t threa
 int pm_tune_set(int op, unsigned log2n, unsigned logc);
 int pm_tune_get(int op, unsigned log2n);   /* current logc, or PM_EINVAL */
 
+/*
+ * Small-batch plans: a batch too small to fill the GPU with 16-word threads
+ * (a single transform or product is latency-bound: a row of 2^logc words
+ * runs on one CU) can use a plan with 4 words per thread in the row pass
+ * (rounds of two stages, four times the threads per row) and shorter rows,
+ * spreading one transform over more CUs; this is the role of the paper's
+ * latency-optimised single- and multi-block kernels (Sec. V-A, V-B).
+ * pm_tune_set_small installs (logc, words_per_thread) for (op, N):
+ * words_per_thread 4 needs 5 <= logc <= 12 (pm_polymul_fused keeps 16),
+ * 16 any valid split; logc = 0 removes the plan. A call over
+ * N * limbs * polys_per_limb <= pm_tune_get_small_batch() words uses the
+ * small-batch plan of its (op, N) if one is installed; the threshold is 0
+ * (no small-batch plans used) until pm_tune_set_small_batch sets it. Results
+ * are identical under every plan; workspace sizes follow the plan in use.
+ */
+int pm_tune_set_small(int op, unsigned log2n, unsigned logc, unsigned words_per_thread);
+int pm_tune_get_small(int op, unsigned log2n, unsigned *logc, unsigned *words_per_thread);
+int pm_tune_set_small_batch(size_t max_words);
+size_t pm_tune_get_small_batch(void);
+
 /* ------------------------------------------------------------- kernel timing
  * While enabled, every kernel the library launches is bracketed by two HIP
  * events recorded on the launch's own stream (the measurement a profiler

@@ -20,6 +20,9 @@
 // four stages are radix-16 in registers. Rounds exchange data through LDS.
 // The last round always holds bits [0, 4) (16 consecutive words per thread);
 // when c is not a multiple of 4 it runs only the remaining c mod 4 stages.
+// The small-batch geometry does the same with rounds of two stages and 4
+// words per thread: four times the threads per row, for batches too small
+// to fill the GPU with 16-word threads.
 //
 // Column pass. One thread per column holds the R = 2^s words of that column
 // in registers and runs the s column stages; twiddles are uniform per launch.
@@ -29,21 +32,30 @@
 
 namespace pm {
 
-template <int LOGC>
+// Row geometry code GEO: bits [0, 5) = c (row of 2^c words); bit 5 set =
+// rounds of two stages with 4 words per thread (the small-batch geometry,
+// more threads per row), clear = rounds of four stages with 16 words per
+// thread. For the 16-word geometry GEO = c.
+constexpr int row_geo(int logc, int ebx) { return logc | (ebx == 2 ? 32 : 0); }
+
+template <int GEO>
 struct RowGeom {
-  static constexpr int EB = LOGC < 4 ? LOGC : 4;      // log2(words per thread)
+  static constexpr int LC = GEO & 31;                  // log2(row length)
+  static constexpr int EBX = (GEO & 32) ? 2 : 4;       // index bits per round
+  static constexpr int EB = LC < EBX ? LC : EBX;       // log2(words per thread)
   static constexpr int E = 1 << EB;
-  static constexpr int LOGT = LOGC - EB;
+  static constexpr int LOGT = LC - EB;
   static constexpr int T = 1 << LOGT;                  // threads per row
-  static constexpr int NR = LOGC <= 4 ? 1 : (LOGC + 3) / 4;   // rounds
-  static constexpr int WG = T < 256 ? 256 : T;         // threads per workgroup
+  static constexpr int NR = LC <= EBX ? 1 : (LC + EBX - 1) / EBX;   // rounds
+  static constexpr int WGMIN = EBX == 4 ? 256 : 64;
+  static constexpr int WG = T < WGMIN ? WGMIN : T;     // threads per workgroup
   static constexpr int ROWS = WG / T;                  // rows per workgroup
-  static constexpr int LDS_ROW = (1 << LOGC) + ((1 << LOGC) >> 4);  // padded words
+  static constexpr int LDS_ROW = (1 << LC) + ((1 << LC) >> 4);  // padded words
   static constexpr int LDS_WORDS = NR > 1 ? ROWS * LDS_ROW : 1;
   // register-bit base p and butterfly bits [lo, hi) of round rho (forward order)
-  static constexpr int hi(int rho) { return LOGC - 4 * rho; }
-  static constexpr int lo(int rho) { return hi(rho) - 4 > 0 ? hi(rho) - 4 : 0; }
-  static constexpr int p(int rho) { return rho == NR - 1 ? 0 : hi(rho) - 4; }
+  static constexpr int hi(int rho) { return LC - EBX * rho; }
+  static constexpr int lo(int rho) { return hi(rho) - EBX > 0 ? hi(rho) - EBX : 0; }
+  static constexpr int p(int rho) { return rho == NR - 1 ? 0 : hi(rho) - EBX; }
 };
 
 // Index inside the row of register j of thread t when the register bits are [p, p+EB).
@@ -64,40 +76,48 @@ __device__ __forceinline__ void stage_fence() {
 }
 
 // LDS slot of row word idx is idx + idx/16: one pad word per 16 keeps strided
-// 64-bit accesses spread over the banks. With idx = th*2^(P+4) + j*2^P + tl
-// (tl < 2^P) the slot splits into a per-thread base plus a per-register
-// constant, so every LDS access is one instruction with an immediate offset:
-//   slot = [th*(2^(P+4) + 2^P) + tl + tl/16] + [j*2^P + (j*2^P)/16]
-// (for P < 4, tl/16 = 0 and (j*2^P + tl)/16 = (j*2^P)/16 since tl < 2^P).
-template <int P>
+// 64-bit accesses spread over the banks. With idx = th*2^(P+EB) + j*2^P + tl
+// (tl < 2^P, j < 2^EB) the slot splits into a per-thread base plus a
+// per-register constant, so every LDS access is one instruction with an
+// immediate offset:
+//   slot = [a + a/16 + tl + tl/16] + [j*2^P + (j*2^P)/16],  a = th*2^(P+EB)
+// (exact for every round of both geometries: the low part j*2^P + tl never
+// carries into the next multiple of 16 above a). For EB = 4, a + a/16 =
+// th*(2^(P+4) + 2^P).
+template <int P, int EB>
 __device__ __forceinline__ uint32_t lds_base(uint32_t t) {
   const uint32_t th = t >> P, tl = t & ((1u << P) - 1u);
-  return th * ((16u << P) + (1u << P)) + tl + (tl >> 4);
+  if constexpr (EB == 4) {
+    return th * ((16u << P) + (1u << P)) + tl + (tl >> 4);
+  } else {
+    const uint32_t a = th << (P + EB);
+    return a + (a >> 4) + tl + (tl >> 4);
+  }
 }
 template <int P>
 __device__ __forceinline__ constexpr uint32_t lds_off(uint32_t j) {
   return (j << P) + ((j << P) >> 4);
 }
 // Row offset of register j: per-thread base plus a per-register constant.
-template <int P>
+template <int P, int EB>
 __device__ __forceinline__ uint32_t row_base(uint32_t t) {
-  return ((t >> P) << (P + 4)) | (t & ((1u << P) - 1u));
+  return ((t >> P) << (P + EB)) | (t & ((1u << P) - 1u));
 }
 
 // Forward (CT) stages of round RHO on registers x. tw = psi_br of this limb,
 // Rr = R + r for row r of an R-row split.
 // TRUNC drops the stride-1 stage (the last of Alg. 5): the truncated CT NTT
 // of the fused product (Sec. III-B).
-template <int LOGC, int RHO, int KIND, bool TRUNC = false, typename W, typename MT>
-__device__ __forceinline__ void fwd_round(W (&x)[RowGeom<LOGC>::E], uint32_t t, const W* __restrict__ tw,
+template <int GEO, int RHO, int KIND, bool TRUNC = false, typename W, typename MT>
+__device__ __forceinline__ void fwd_round(W (&x)[RowGeom<GEO>::E], uint32_t t, const W* __restrict__ tw,
                                           uint32_t Rr, const MT& M) {
-  using G = RowGeom<LOGC>;
+  using G = RowGeom<GEO>;
   constexpr int P = G::p(RHO), HI = G::hi(RHO), LO = (TRUNC && G::lo(RHO) == 0) ? 1 : G::lo(RHO), EB = G::EB;
   const uint32_t th = t >> P;
 #pragma unroll
   for (int b = HI - 1; b >= LO; --b) {
     const int jb = b - P;                          // register bit paired at this stage
-    const uint32_t mm = 1u << (LOGC - b - 1);      // groups per row at this stage
+    const uint32_t mm = 1u << (G::LC - b - 1);      // groups per row at this stage
     const uint32_t base = Rr * mm + (th << (P + EB - b - 1));
 #pragma unroll
     for (int g = 0; g < (G::E >> (jb + 1)); ++g) {
@@ -115,16 +135,16 @@ __device__ __forceinline__ void fwd_round(W (&x)[RowGeom<LOGC>::E], uint32_t t, 
 // Inverse (GS, halved) stages of round RHO, smallest stride first. TRUNC drops
 // the stride-1 stage (the first of Alg. 6): the truncated GS NTT of the fused
 // product, whose first stage and its 1/2 are folded into Alg. 7.
-template <int LOGC, int RHO, int KIND, bool TRUNC = false, typename W, typename MT>
-__device__ __forceinline__ void inv_round(W (&x)[RowGeom<LOGC>::E], uint32_t t, const W* __restrict__ tw,
+template <int GEO, int RHO, int KIND, bool TRUNC = false, typename W, typename MT>
+__device__ __forceinline__ void inv_round(W (&x)[RowGeom<GEO>::E], uint32_t t, const W* __restrict__ tw,
                                           uint32_t Rr, const MT& M) {
-  using G = RowGeom<LOGC>;
+  using G = RowGeom<GEO>;
   constexpr int P = G::p(RHO), HI = G::hi(RHO), LO = (TRUNC && G::lo(RHO) == 0) ? 1 : G::lo(RHO), EB = G::EB;
   const uint32_t th = t >> P;
 #pragma unroll
   for (int b = LO; b < HI; ++b) {
     const int jb = b - P;
-    const uint32_t mm = 1u << (LOGC - b - 1);
+    const uint32_t mm = 1u << (G::LC - b - 1);
     const uint32_t base = Rr * mm + (th << (P + EB - b - 1));
 #pragma unroll
     for (int g = 0; g < (G::E >> (jb + 1)); ++g) {
@@ -139,78 +159,76 @@ __device__ __forceinline__ void inv_round(W (&x)[RowGeom<LOGC>::E], uint32_t t, 
   }
 }
 
-// LDS and global accesses below only run for rows with at least two rounds
-// (LOGC > 4), where every round's register bits are 4 wide (EB = 4); for
-// LOGC <= 4 the single round has P = 0 and EB = LOGC, and the same formulas
-// hold with 2^(P+4) replaced by 2^EB, which row_base/lds_base never need
-// because th = 0 there (one thread per row).
-template <int LOGC, int RHO, typename W>
-__device__ __forceinline__ void lds_put(W* lds, const W (&x)[RowGeom<LOGC>::E], uint32_t t) {
-  using G = RowGeom<LOGC>;
+// LDS exchanges only run for rows of at least two rounds, where every round's
+// register bits are EB = EBX wide; a single-round row (c <= EBX) has P = 0
+// and one thread per row, so its global accesses use t << EB directly.
+template <int GEO, int RHO, typename W>
+__device__ __forceinline__ void lds_put(W* lds, const W (&x)[RowGeom<GEO>::E], uint32_t t) {
+  using G = RowGeom<GEO>;
   constexpr int P = G::p(RHO);
-  W* b = lds + lds_base<P>(t);
+  W* b = lds + lds_base<P, G::EB>(t);
 #pragma unroll
   for (int j = 0; j < G::E; ++j) b[lds_off<P>(j)] = x[j];
 }
 
-template <int LOGC, int RHO, typename W>
-__device__ __forceinline__ void lds_get(const W* lds, W (&x)[RowGeom<LOGC>::E], uint32_t t) {
-  using G = RowGeom<LOGC>;
+template <int GEO, int RHO, typename W>
+__device__ __forceinline__ void lds_get(const W* lds, W (&x)[RowGeom<GEO>::E], uint32_t t) {
+  using G = RowGeom<GEO>;
   constexpr int P = G::p(RHO);
-  const W* b = lds + lds_base<P>(t);
+  const W* b = lds + lds_base<P, G::EB>(t);
 #pragma unroll
   for (int j = 0; j < G::E; ++j) x[j] = b[lds_off<P>(j)];
 }
 
-template <int LOGC, int RHO, typename W>
-__device__ __forceinline__ void gmem_get(const W* __restrict__ row, W (&x)[RowGeom<LOGC>::E], uint32_t t) {
-  using G = RowGeom<LOGC>;
+template <int GEO, int RHO, typename W>
+__device__ __forceinline__ void gmem_get(const W* __restrict__ row, W (&x)[RowGeom<GEO>::E], uint32_t t) {
+  using G = RowGeom<GEO>;
   constexpr int P = G::p(RHO);
-  const uint32_t tb = (G::NR > 1) ? row_base<P>(t) : (t << G::EB);
+  const uint32_t tb = (G::NR > 1) ? row_base<P, G::EB>(t) : (t << G::EB);
 #pragma unroll
   for (int j = 0; j < G::E; ++j) x[j] = (row + (j << P))[tb];
 }
 
-template <int LOGC, int RHO, typename W>
-__device__ __forceinline__ void gmem_put(W* __restrict__ row, const W (&x)[RowGeom<LOGC>::E], uint32_t t) {
-  using G = RowGeom<LOGC>;
+template <int GEO, int RHO, typename W>
+__device__ __forceinline__ void gmem_put(W* __restrict__ row, const W (&x)[RowGeom<GEO>::E], uint32_t t) {
+  using G = RowGeom<GEO>;
   constexpr int P = G::p(RHO);
-  const uint32_t tb = (G::NR > 1) ? row_base<P>(t) : (t << G::EB);
+  const uint32_t tb = (G::NR > 1) ? row_base<P, G::EB>(t) : (t << G::EB);
 #pragma unroll
   for (int j = 0; j < G::E; ++j) (row + (j << P))[tb] = x[j];
 }
 
 // Move registers from round FROM's layout to round TO's layout through LDS.
 // All threads of the workgroup must call it (it holds two barriers).
-template <int LOGC, int FROM, int TO, typename W>
-__device__ __forceinline__ void exchange(W* lds, W (&x)[RowGeom<LOGC>::E], uint32_t t) {
+template <int GEO, int FROM, int TO, typename W>
+__device__ __forceinline__ void exchange(W* lds, W (&x)[RowGeom<GEO>::E], uint32_t t) {
   __syncthreads();
-  lds_put<LOGC, FROM>(lds, x, t);
+  lds_put<GEO, FROM>(lds, x, t);
   __syncthreads();
-  lds_get<LOGC, TO>(lds, x, t);
+  lds_get<GEO, TO>(lds, x, t);
 }
 
 // All row stages of the forward transform: rounds 0..NR-1. On return x holds
-// the row in the last round's layout (16 consecutive words per thread).
-template <int LOGC, int KIND, int RHO = 0, bool TRUNC = false, typename W, typename MT>
-__device__ __forceinline__ void fwd_rounds(W* lds, W (&x)[RowGeom<LOGC>::E], uint32_t t, const W* __restrict__ tw,
+// the row in the last round's layout (E consecutive words per thread).
+template <int GEO, int KIND, int RHO = 0, bool TRUNC = false, typename W, typename MT>
+__device__ __forceinline__ void fwd_rounds(W* lds, W (&x)[RowGeom<GEO>::E], uint32_t t, const W* __restrict__ tw,
                                            uint32_t Rr, const MT& M) {
-  fwd_round<LOGC, RHO, KIND, TRUNC>(x, t, tw, Rr, M);
-  if constexpr (RHO + 1 < RowGeom<LOGC>::NR) {
-    exchange<LOGC, RHO, RHO + 1>(lds, x, t);
-    fwd_rounds<LOGC, KIND, RHO + 1, TRUNC>(lds, x, t, tw, Rr, M);
+  fwd_round<GEO, RHO, KIND, TRUNC>(x, t, tw, Rr, M);
+  if constexpr (RHO + 1 < RowGeom<GEO>::NR) {
+    exchange<GEO, RHO, RHO + 1>(lds, x, t);
+    fwd_rounds<GEO, KIND, RHO + 1, TRUNC>(lds, x, t, tw, Rr, M);
   }
 }
 
 // All row stages of the inverse transform, from the last round's layout back
 // to round 0's layout.
-template <int LOGC, int KIND, int RHO = RowGeom<LOGC>::NR - 1, bool TRUNC = false, typename W, typename MT>
-__device__ __forceinline__ void inv_rounds(W* lds, W (&x)[RowGeom<LOGC>::E], uint32_t t, const W* __restrict__ tw,
+template <int GEO, int KIND, int RHO = RowGeom<GEO>::NR - 1, bool TRUNC = false, typename W, typename MT>
+__device__ __forceinline__ void inv_rounds(W* lds, W (&x)[RowGeom<GEO>::E], uint32_t t, const W* __restrict__ tw,
                                            uint32_t Rr, const MT& M) {
-  inv_round<LOGC, RHO, KIND, TRUNC>(x, t, tw, Rr, M);
+  inv_round<GEO, RHO, KIND, TRUNC>(x, t, tw, Rr, M);
   if constexpr (RHO > 0) {
-    exchange<LOGC, RHO, RHO - 1>(lds, x, t);
-    inv_rounds<LOGC, KIND, RHO - 1, TRUNC>(lds, x, t, tw, Rr, M);
+    exchange<GEO, RHO, RHO - 1>(lds, x, t);
+    inv_rounds<GEO, KIND, RHO - 1, TRUNC>(lds, x, t, tw, Rr, M);
   }
 }
 
@@ -221,27 +239,27 @@ __device__ __forceinline__ void inv_rounds(W* lds, W (&x)[RowGeom<LOGC>::E], uin
 // twiddle is the stride-2 twiddle of the same word, index (R+r)*C/4 + idx/4,
 // and the sign is fixed per register because 16t and r*C are multiples of 4.
 // Needs C >= 4. Results overwrite x.
-template <int LOGC, typename W>
+template <int GEO, typename W>
 struct FusedTw {
-  W v[RowGeom<LOGC>::E / 4 > 0 ? RowGeom<LOGC>::E / 4 : 1];
+  W v[RowGeom<GEO>::E / 4 > 0 ? RowGeom<GEO>::E / 4 : 1];
 };
 
 // The alpha^2 twiddles of a thread's pairs, loaded ahead of use.
-template <int LOGC, typename W>
-__device__ __forceinline__ FusedTw<LOGC, W> fused_twiddles(uint32_t t, const W* __restrict__ tw, uint32_t Rr) {
-  using G = RowGeom<LOGC>;
-  static_assert(LOGC >= 2, "the fused product needs rows of at least 4 words");
-  FusedTw<LOGC, W> f;
-  const uint32_t base = Rr * (1u << (LOGC - 2)) + (t << (G::EB - 2));
+template <int GEO, typename W>
+__device__ __forceinline__ FusedTw<GEO, W> fused_twiddles(uint32_t t, const W* __restrict__ tw, uint32_t Rr) {
+  using G = RowGeom<GEO>;
+  static_assert(G::LC >= 2, "the fused product needs rows of at least 4 words");
+  FusedTw<GEO, W> f;
+  const uint32_t base = Rr * (1u << (G::LC - 2)) + (t << (G::EB - 2));
 #pragma unroll
   for (int g = 0; g < G::E / 4; ++g) f.v[g] = tw[base + g];
   return f;
 }
 
-template <int LOGC, int KIND, typename W, typename MT>
-__device__ __forceinline__ void fused_hadamard(W (&x)[RowGeom<LOGC>::E], const W (&y)[RowGeom<LOGC>::E],
-                                               const FusedTw<LOGC, W>& f, const MT& M) {
-  using G = RowGeom<LOGC>;
+template <int GEO, int KIND, typename W, typename MT>
+__device__ __forceinline__ void fused_hadamard(W (&x)[RowGeom<GEO>::E], const W (&y)[RowGeom<GEO>::E],
+                                               const FusedTw<GEO, W>& f, const MT& M) {
+  using G = RowGeom<GEO>;
 #pragma unroll
   for (int j = 0; j < G::E; j += 2) {
     const W xi = f.v[j >> 2];

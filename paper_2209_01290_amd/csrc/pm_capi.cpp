@@ -133,15 +133,18 @@ int check_ptr(const void* p, const char* name) {
 }
 
 // Launch wrappers that name each kernel for the event timer.
-const char* row_name(int mode, int logc) {
+// Row kernel names: row_<mode>_c<logc>, with a trailing "s" for the
+// small-batch geometry (4 words per thread).
+const char* row_name(int mode, int logc, int ebx = 4) {
   static std::vector<std::string> names = [] {
     std::vector<std::string> v;
     const char* m[5] = {"row_fwd_c", "row_inv_c", "row_mul_c", "row_sqr_c", "row_fmul_c"};
-    for (int i = 0; i < 5; ++i)
-      for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c));
+    for (int g = 0; g < 2; ++g)
+      for (int i = 0; i < 5; ++i)
+        for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c) + (g ? "s" : ""));
     return v;
   }();
-  return names[mode * 15 + logc].c_str();
+  return names[(ebx == 2 ? 75 : 0) + mode * 15 + logc].c_str();
 }
 
 const char* col_name(bool inv, int logr) {
@@ -154,9 +157,9 @@ const char* col_name(bool inv, int logr) {
   return names[(inv ? 6 : 0) + logr].c_str();
 }
 
-hipError_t run_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s) {
-  ProfScope ps(s, row_name(mode, logc));
-  return launch_row(logc, kind, mode, a, s);
+hipError_t run_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s, int ebx = 4) {
+  ProfScope ps(s, row_name(mode, logc, ebx));
+  return launch_row(logc, kind, mode, a, s, ebx);
 }
 
 hipError_t run_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_t s) {
@@ -223,15 +226,16 @@ int check_ptr32(const void* p, const char* name) {
   return PM_OK;
 }
 
-const char* row_name32(int mode, int logc) {
+const char* row_name32(int mode, int logc, int ebx = 4) {
   static std::vector<std::string> names = [] {
     std::vector<std::string> v;
     const char* m[3] = {"row32_fwd_c", "row32_inv_c", "row32_mul_c"};
-    for (int i = 0; i < 3; ++i)
-      for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c));
+    for (int g = 0; g < 2; ++g)
+      for (int i = 0; i < 3; ++i)
+        for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c) + (g ? "s" : ""));
     return v;
   }();
-  return names[mode * 15 + logc].c_str();
+  return names[(ebx == 2 ? 45 : 0) + mode * 15 + logc].c_str();
 }
 
 const char* col_name32(bool inv, int logr) {
@@ -244,9 +248,9 @@ const char* col_name32(bool inv, int logr) {
   return names[(inv ? 6 : 0) + logr].c_str();
 }
 
-hipError_t run_row32(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s) {
-  ProfScope ps(s, row_name32(mode, logc));
-  return launch_row(logc, kind, mode, a, s);
+hipError_t run_row32(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s, int ebx = 4) {
+  ProfScope ps(s, row_name32(mode, logc, ebx));
+  return launch_row(logc, kind, mode, a, s, ebx);
 }
 
 hipError_t run_col32(int logr, int kind, bool inv, const ColArgsT<uint32_t>& a, hipStream_t s) {
@@ -298,7 +302,7 @@ static int ntt_common(uint64_t* x, size_t N, size_t limbs, size_t polys, const u
   int rc;
   if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
   if ((rc = check_ptr(x, "x")) || (rc = check_ptr(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
-  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n);
+  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n, N * limbs * polys);
   hipStream_t s = (hipStream_t)stream;
   rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
     const size_t base = l0 * polys * N;
@@ -310,9 +314,9 @@ static int ntt_common(uint64_t* x, size_t N, size_t limbs, size_t polys, const u
     hipError_t e;
     if (!inv) {
       if (p.R > 1 && (e = run_col(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
-      return run_row(p.logc, b.kind, ROW_FWD, ra, s);
+      return run_row(p.logc, b.kind, ROW_FWD, ra, s, p.ebx);
     }
-    if ((e = run_row(p.logc, b.kind, ROW_INV, ra, s)) != hipSuccess) return e;
+    if ((e = run_row(p.logc, b.kind, ROW_INV, ra, s, p.ebx)) != hipSuccess) return e;
     if (p.R > 1) return run_col(p.logr, b.kind, true, ca, s);
     return hipSuccess;
   });
@@ -332,7 +336,7 @@ int pm_ntt_inv(uint64_t* x, size_t N, size_t limbs, size_t polys_per_limb, const
 
 size_t pm_polymul_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {
   if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N)) return 0;
-  const PassPlan p = plan_for(OP_POLYMUL, log2u(N));
+  const PassPlan p = plan_for(OP_POLYMUL, log2u(N), N * limbs * polys_per_limb);
   return p.R > 1 ? N * limbs * polys_per_limb * sizeof(uint64_t) : 0;
 }
 
@@ -346,11 +350,15 @@ static int polymul_common(const uint64_t* a, const uint64_t* b_, uint64_t* c, si
   if ((rc = check_ptr(a, "a")) || (rc = check_ptr(b_, "b")) || (rc = check_ptr(c, "c")) ||
       (rc = check_ptr(psi_br, "psi_br")) || (rc = check_ptr(psi_inv_br, "psi_inv_br")))
     return rc;
-  const PassPlan p = plan_for(OP_POLYMUL, b.log2n);
+  const PassPlan p = plan_for(OP_POLYMUL, b.log2n, N * limbs * polys);
   // the fused product needs N >= 4 (Alg. 8's squared-twiddle identity)
   fused = fused && b.log2n >= 2;
   const bool same = (a == b_);          // one operand: one column pass, no workspace
-  const bool square = same && !fused;   // and, unfused, one row transform
+  // and, unfused, one row transform (the small-batch geometry has no squaring
+  // mode: it runs the product with b = a)
+  const bool square = same && !fused && p.ebx == 4;
+  // the fused rows exist in the 16-word geometry only
+  const int ebx = fused ? 4 : (int)p.ebx;
   // The product is commutative: when c aliases b, swap so that c aliases a.
   const uint64_t* A = a;
   const uint64_t* B = b_;
@@ -367,7 +375,7 @@ static int polymul_common(const uint64_t* a, const uint64_t* b_, uint64_t* c, si
     if (p.R == 1) {
       RowArgs ra{A + base, square ? nullptr : B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys,
                  (uint32_t)nl, &ls};
-      return run_row(p.logc, b.kind, fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL), ra, s);
+      return run_row(p.logc, b.kind, fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL), ra, s, ebx);
     }
     // column stages of a (-> c) and b (-> workspace), fused rows, inverse columns of c
     uint64_t* wb = same ? c + base : ws + base;
@@ -377,7 +385,7 @@ static int polymul_common(const uint64_t* a, const uint64_t* b_, uint64_t* c, si
     if (e != hipSuccess) return e;
     RowArgs ra{c + base, square ? nullptr : wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl,
                &ls};
-    if ((e = run_row(p.logc, b.kind, fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL), ra, s)) != hipSuccess)
+    if ((e = run_row(p.logc, b.kind, fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL), ra, s, ebx)) != hipSuccess)
       return e;
     ColArgs ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
     return run_col(p.logr, b.kind, true, ci, s);
@@ -453,7 +461,7 @@ static int ntt_common32(uint32_t* x, size_t N, size_t limbs, size_t polys, const
   int rc;
   if ((rc = check_batch32(&b, N, limbs, polys, q))) return rc;
   if ((rc = check_ptr32(x, "x")) || (rc = check_ptr32(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
-  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n);
+  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n, N * limbs * polys);
   hipStream_t s = (hipStream_t)stream;
   rc = for_chunks32(b, [&](size_t l0, size_t nl, const LimbSet32& ls) -> hipError_t {
     uint32_t* xs = x + l0 * polys * N;
@@ -464,9 +472,9 @@ static int ntt_common32(uint32_t* x, size_t N, size_t limbs, size_t polys, const
     hipError_t e;
     if (!inv) {
       if (p.R > 1 && (e = run_col32(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
-      return run_row32(p.logc, b.kind, ROW_FWD, ra, s);
+      return run_row32(p.logc, b.kind, ROW_FWD, ra, s, p.ebx);
     }
-    if ((e = run_row32(p.logc, b.kind, ROW_INV, ra, s)) != hipSuccess) return e;
+    if ((e = run_row32(p.logc, b.kind, ROW_INV, ra, s, p.ebx)) != hipSuccess) return e;
     if (p.R > 1) return run_col32(p.logr, b.kind, true, ca, s);
     return hipSuccess;
   });
@@ -486,7 +494,7 @@ int pm_ntt_inv_u32(uint32_t* x, size_t N, size_t limbs, size_t polys_per_limb, c
 
 size_t pm_polymul_u32_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {
   if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N)) return 0;
-  const PassPlan p = plan_for(OP_POLYMUL, log2u(N));
+  const PassPlan p = plan_for(OP_POLYMUL, log2u(N), N * limbs * polys_per_limb);
   return p.R > 1 ? N * limbs * polys_per_limb * sizeof(uint32_t) : 0;
 }
 
@@ -500,7 +508,7 @@ int pm_polymul_u32(const uint32_t* a, const uint32_t* b_, uint32_t* c, size_t N,
   if ((rc = check_ptr32(a, "a")) || (rc = check_ptr32(b_, "b")) || (rc = check_ptr32(c, "c")) ||
       (rc = check_ptr32(psi_br, "psi_br")) || (rc = check_ptr32(psi_inv_br, "psi_inv_br")))
     return rc;
-  const PassPlan p = plan_for(OP_POLYMUL, b.log2n);
+  const PassPlan p = plan_for(OP_POLYMUL, b.log2n, N * limbs * polys);
   const bool same = (a == b_);          // one operand: one column pass, no workspace
   const uint32_t* A = a;
   const uint32_t* B = b_;
@@ -514,7 +522,7 @@ int pm_polymul_u32(const uint32_t* a, const uint32_t* b_, uint32_t* c, size_t N,
     const uint32_t* ti = psi_inv_br + l0 * N;
     if (p.R == 1) {
       RowArgsT<uint32_t> ra{A + base, B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys, (uint32_t)nl, &ls};
-      return run_row32(p.logc, b.kind, ROW_MUL, ra, s);
+      return run_row32(p.logc, b.kind, ROW_MUL, ra, s, p.ebx);
     }
     uint32_t* wb = same ? c + base : ws + base;
     ColArgsT<uint32_t> cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
@@ -522,7 +530,7 @@ int pm_polymul_u32(const uint32_t* a, const uint32_t* b_, uint32_t* c, size_t N,
     hipError_t e = run_col32(p.logr, b.kind, false, cf, s);
     if (e != hipSuccess) return e;
     RowArgsT<uint32_t> ra{c + base, wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl, &ls};
-    if ((e = run_row32(p.logc, b.kind, ROW_MUL, ra, s)) != hipSuccess) return e;
+    if ((e = run_row32(p.logc, b.kind, ROW_MUL, ra, s, p.ebx)) != hipSuccess) return e;
     ColArgsT<uint32_t> ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1,
                           &ls};
     return run_col32(p.logr, b.kind, true, ci, s);

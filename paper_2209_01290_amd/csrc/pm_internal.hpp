@@ -52,11 +52,14 @@ using ColArgs = ColArgsT<uint64_t>;
 
 hipError_t launch_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t n, const Mod& M, int kind,
                          hipStream_t s);
-hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s);
-hipError_t launch_row(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s);
-#define PM_DECL_ROW(L)                                                                        \
-  hipError_t launch_row_##L(int kind, int mode, const RowArgs& a, hipStream_t s);             \
-  hipError_t launch_row_##L(int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s);
+// ebx: log2 of the words per thread of the row pass: 4 (16 words, rounds of
+// four stages) or 2 (4 words, rounds of two stages; rows of 2^5..2^12, modes
+// FWD, INV and MUL only).
+hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s, int ebx = 4);
+hipError_t launch_row(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s, int ebx = 4);
+#define PM_DECL_ROW(L)                                                                               \
+  hipError_t launch_row_##L(int kind, int mode, int ebx, const RowArgs& a, hipStream_t s);           \
+  hipError_t launch_row_##L(int kind, int mode, int ebx, const RowArgsT<uint32_t>& a, hipStream_t s);
 PM_DECL_ROW(1) PM_DECL_ROW(2) PM_DECL_ROW(3) PM_DECL_ROW(4) PM_DECL_ROW(5) PM_DECL_ROW(6) PM_DECL_ROW(7)
 PM_DECL_ROW(8) PM_DECL_ROW(9) PM_DECL_ROW(10) PM_DECL_ROW(11) PM_DECL_ROW(12) PM_DECL_ROW(13) PM_DECL_ROW(14)
 #undef PM_DECL_ROW

@@ -101,9 +101,9 @@ hipError_t launch_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size
 }
 
 template <typename A>
-static hipError_t launch_row_any(int logc, int kind, int mode, const A& a, hipStream_t s) {
+static hipError_t launch_row_any(int logc, int kind, int mode, int ebx, const A& a, hipStream_t s) {
   switch (logc) {
-#define PM_ROW_CASE(L) case L: return launch_row_##L(kind, mode, a, s);
+#define PM_ROW_CASE(L) case L: return launch_row_##L(kind, mode, ebx, a, s);
     PM_ROW_CASE(1) PM_ROW_CASE(2) PM_ROW_CASE(3) PM_ROW_CASE(4) PM_ROW_CASE(5) PM_ROW_CASE(6)
     PM_ROW_CASE(7) PM_ROW_CASE(8) PM_ROW_CASE(9) PM_ROW_CASE(10) PM_ROW_CASE(11) PM_ROW_CASE(12)
     PM_ROW_CASE(13) PM_ROW_CASE(14)
@@ -112,12 +112,12 @@ static hipError_t launch_row_any(int logc, int kind, int mode, const A& a, hipSt
   }
 }
 
-hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s) {
-  return launch_row_any(logc, kind, mode, a, s);
+hipError_t launch_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s, int ebx) {
+  return launch_row_any(logc, kind, mode, ebx, a, s);
 }
 
-hipError_t launch_row(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s) {
-  return launch_row_any(logc, kind, mode, a, s);
+hipError_t launch_row(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s, int ebx) {
+  return launch_row_any(logc, kind, mode, ebx, a, s);
 }
 
 template <int LOGR, int KIND, typename W>

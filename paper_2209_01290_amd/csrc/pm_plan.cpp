@@ -11,6 +11,15 @@ namespace {
 
 // logc per (op, log2n); 0 = use the default rule.
 std::atomic<uint32_t> g_logc[OP_COUNT][PM_MAX_LOG2N + 1];
+// small-batch plans: logc | ebx << 8 per (op, log2n); 0 = none installed
+std::atomic<uint32_t> g_small[OP_COUNT][PM_MAX_LOG2N + 1];
+std::atomic<size_t> g_small_words{0};
+
+bool valid_split(unsigned log2n, unsigned logc) {
+  if (logc > log2n || logc > PM_MAX_LOGC || log2n - logc > PM_MAX_LOGR) return false;
+  if (logc < log2n && logc < 8) return false;   // column pass needs >= 256 columns
+  return true;
+}
 
 uint32_t default_logc(int op, unsigned log2n) {
   // Rows of 2^12 words (32 KiB of LDS, 256 threads) keep four workgroups per
@@ -26,11 +35,31 @@ uint32_t default_logc(int op, unsigned log2n) {
 bool plan_set(int op, unsigned log2n, unsigned logc) {
   if (op < 0 || op >= OP_COUNT || log2n < 1 || log2n > PM_MAX_LOG2N) return false;
   if (logc == 0) { g_logc[op][log2n].store(0); return true; }
-  if (logc > log2n || logc > PM_MAX_LOGC || log2n - logc > PM_MAX_LOGR) return false;
-  if (logc < log2n && logc < 8) return false;   // column pass needs >= 256 columns
+  if (!valid_split(log2n, logc)) return false;
   g_logc[op][log2n].store(logc);
   return true;
 }
+
+bool plan_small_set(int op, unsigned log2n, unsigned logc, unsigned ebx) {
+  if (op < 0 || op >= OP_COUNT || log2n < 1 || log2n > PM_MAX_LOG2N) return false;
+  if (logc == 0) { g_small[op][log2n].store(0); return true; }
+  if (ebx != 2 && ebx != 4) return false;
+  if (!valid_split(log2n, logc)) return false;
+  if (ebx == 2 && (logc < 5 || logc > 12)) return false;
+  g_small[op][log2n].store(logc | (ebx << 8));
+  return true;
+}
+
+bool plan_small_get(int op, unsigned log2n, unsigned* logc, unsigned* ebx) {
+  if (op < 0 || op >= OP_COUNT || log2n < 1 || log2n > PM_MAX_LOG2N) return false;
+  const uint32_t v = g_small[op][log2n].load();
+  *logc = v & 0xff;
+  *ebx = v ? v >> 8 : 0;
+  return true;
+}
+
+void plan_small_threshold_set(size_t words) { g_small_words.store(words); }
+size_t plan_small_threshold() { return g_small_words.load(); }
 
 PassPlan plan_for(int op, unsigned log2n) {
   uint32_t logc = g_logc[op][log2n].load();
@@ -39,7 +68,23 @@ PassPlan plan_for(int op, unsigned log2n) {
   p.logc = logc;
   p.logr = log2n - logc;
   p.R = 1u << p.logr;
+  p.ebx = 4;
   return p;
+}
+
+PassPlan plan_for(int op, unsigned log2n, size_t batch_words) {
+  if (batch_words <= g_small_words.load()) {
+    const uint32_t v = g_small[op][log2n].load();
+    if (v) {
+      PassPlan p;
+      p.logc = v & 0xff;
+      p.logr = log2n - p.logc;
+      p.R = 1u << p.logr;
+      p.ebx = v >> 8;
+      return p;
+    }
+  }
+  return plan_for(op, log2n);
 }
 
 }  // namespace pm
@@ -52,3 +97,24 @@ extern "C" int pm_tune_get(int op, unsigned log2n) {
   if (op < 0 || op >= pm::OP_COUNT || log2n < 1 || log2n > pm::PM_MAX_LOG2N) return PM_EINVAL;
   return (int)pm::plan_for(op, log2n).logc;
 }
+
+extern "C" int pm_tune_set_small(int op, unsigned log2n, unsigned logc, unsigned words_per_thread) {
+  const unsigned ebx = words_per_thread == 4 ? 2 : words_per_thread == 16 ? 4 : 0;
+  if (logc != 0 && ebx == 0) return PM_EINVAL;
+  return pm::plan_small_set(op, log2n, logc, ebx) ? PM_OK : PM_EINVAL;
+}
+
+extern "C" int pm_tune_get_small(int op, unsigned log2n, unsigned* logc, unsigned* words_per_thread) {
+  unsigned l, e;
+  if (!logc || !words_per_thread || !pm::plan_small_get(op, log2n, &l, &e)) return PM_EINVAL;
+  *logc = l;
+  *words_per_thread = e ? (1u << e) : 0;
+  return PM_OK;
+}
+
+extern "C" int pm_tune_set_small_batch(size_t max_words) {
+  pm::plan_small_threshold_set(max_words);
+  return PM_OK;
+}
+
+extern "C" size_t pm_tune_get_small_batch(void) { return pm::plan_small_threshold(); }

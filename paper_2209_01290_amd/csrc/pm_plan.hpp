@@ -4,6 +4,7 @@
 // be replaced per (operation, N) at run time (pm_tune_set), which is how the
 // autotuner installs its choices.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace pm {
@@ -16,10 +17,22 @@ enum { OP_NTT_FWD = 0, OP_NTT_INV = 1, OP_POLYMUL = 2, OP_COUNT = 3 };
 
 struct PassPlan {
   uint32_t logc, logr, R;
+  uint32_t ebx;    // row pass: log2 words per thread (4, or 2 for the small-batch geometry)
 };
 
+// The throughput plan (16 words per thread).
 PassPlan plan_for(int op, unsigned log2n);
+// The plan for a call over batch_words = N * limbs * polys words: the
+// small-batch plan of (op, log2n) if one is installed and batch_words is at
+// most the small-batch threshold, else the throughput plan.
+PassPlan plan_for(int op, unsigned log2n, size_t batch_words);
 // Returns false if (op, log2n, logc) is not a valid split.
 bool plan_set(int op, unsigned log2n, unsigned logc);
+// Small-batch plan: logc = 0 removes it; ebx in {2, 4}; ebx = 2 needs
+// 5 <= logc <= 12. Returns false for an invalid split.
+bool plan_small_set(int op, unsigned log2n, unsigned logc, unsigned ebx);
+bool plan_small_get(int op, unsigned log2n, unsigned* logc, unsigned* ebx);
+void plan_small_threshold_set(size_t words);
+size_t plan_small_threshold();
 
 }  // namespace pm

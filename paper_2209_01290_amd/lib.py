@@ -69,6 +69,11 @@ def load():
             "pm_polymul_stagewise_workspace_bytes": (sz, [sz, sz, sz]),
             "pm_tune_set": (i32, [i32, ctypes.c_uint, ctypes.c_uint]),
             "pm_tune_get": (i32, [i32, ctypes.c_uint]),
+            "pm_tune_set_small": (i32, [i32, ctypes.c_uint, ctypes.c_uint, ctypes.c_uint]),
+            "pm_tune_get_small": (i32, [i32, ctypes.c_uint, ctypes.POINTER(ctypes.c_uint),
+                                        ctypes.POINTER(ctypes.c_uint)]),
+            "pm_tune_set_small_batch": (i32, [sz]),
+            "pm_tune_get_small_batch": (sz, []),
             "pm_ntt_primes": (sz, [u64, ctypes.c_uint, sz, u64p]),
             "pm_find_psi": (u64, [u64, sz]),
             "pm_make_tables": (i32, [u64, sz, u64, u64p, u64p]),
@@ -110,7 +115,8 @@ def exported_symbols():
             "pm_plan_destroy", "pm_plan_device_bytes", "pm_reduce_apply", "pm_reduce_chain",
             "pm_ntt_fwd_u32", "pm_ntt_inv_u32", "pm_polymul_u32", "pm_polymul_u32_workspace_bytes",
             "pm_make_tables_u32", "pm_ntt_fwd_il", "pm_ntt_inv_il", "pm_polymul_il",
-            "pm_polymul_il_workspace_bytes"]
+            "pm_polymul_il_workspace_bytes", "pm_tune_set_small", "pm_tune_get_small",
+            "pm_tune_set_small_batch", "pm_tune_get_small_batch"]
 
 
 def _check(rc: int, func: str):
@@ -357,9 +363,30 @@ def pm_tune_get(op, log2n):
     return r
 
 
+def pm_tune_set_small(op, log2n, logc, words_per_thread):
+    _check(load().pm_tune_set_small(op, log2n, logc, words_per_thread), "pm_tune_set_small")
+
+
+def pm_tune_get_small(op, log2n):
+    """(logc, words_per_thread) of the small-batch plan, (0, 0) if none."""
+    lc, wpt = ctypes.c_uint(), ctypes.c_uint()
+    _check(load().pm_tune_get_small(op, log2n, ctypes.byref(lc), ctypes.byref(wpt)), "pm_tune_get_small")
+    return lc.value, wpt.value
+
+
+def pm_tune_set_small_batch(max_words):
+    _check(load().pm_tune_set_small_batch(max_words), "pm_tune_set_small_batch")
+
+
+def pm_tune_get_small_batch():
+    return int(load().pm_tune_get_small_batch())
+
+
 def apply_tune_db(path=None):
-    """Install the pass plans of an autotuner database (see tune.py); returns
-    the number of entries applied, 0 if the file does not exist."""
+    """Install the pass plans of an autotuner database (see tune.py): the
+    throughput plans ("choices") and, if present, the small-batch plans
+    ("small": {"max_words": W, "choices": {op: {log2n: [logc, words_per_thread]}}});
+    returns the number of entries applied, 0 if the file does not exist."""
     import json
     if path is None:
         path = os.path.join(PKG, "tune_db", "gfx950.json")
@@ -373,6 +400,13 @@ def apply_tune_db(path=None):
         for log2n, logc in table.items():
             pm_tune_set(ops[name], int(log2n), int(logc))
             n += 1
+    small = db.get("small")
+    if small:
+        for name, table in small.get("choices", {}).items():
+            for log2n, (logc, wpt) in table.items():
+                pm_tune_set_small(ops[name], int(log2n), int(logc), int(wpt))
+                n += 1
+        pm_tune_set_small_batch(int(small["max_words"]))
     return n
 
 

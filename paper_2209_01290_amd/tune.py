@@ -9,7 +9,17 @@ with pm_tune_set and writes the choices to a JSON database:
     {"arch": "gfx950", "device": "...", "choices": {"polymul": {"16": 12, ...}, ...},
      "timings_ms": {"polymul": {"16": {"12": 0.81, "13": 0.85}, ...}, ...}}
 
-Usage on a GPU:  python -m paper_2209_01290_amd.tune [--out FILE] [--log2n 12-17]
+Small-batch plans (--small): for a single transform or product per call
+(one limb, one polynomial) it times every split with 16 and with 4 words per
+thread (device time per call, 20 calls captured in one HIP graph and
+replayed), keeps the fastest per (operation, N), and finds the largest batch
+(in words) at which the small-batch plan still beats the throughput plan,
+doubling the batch at N = 2^12 and 2^16:
+
+    "small": {"max_words": W, "choices": {"polymul": {"16": [logc, words_per_thread]}, ...},
+              "latency_us": {...}, "crossover_us": {...}}
+
+Usage on a GPU:  python -m paper_2209_01290_amd.tune [--out FILE] [--log2n 12-17] [--small]
 Applying a database: lib.apply_tune_db(FILE) (bench.py and serve.py do).
 """
 from __future__ import annotations
@@ -93,13 +103,133 @@ def tune(log2ns, words=1 << 25, device="cuda", verbose=True):
             "batch_words": words, "choices": choices, "timings_ms": timings}
 
 
+def small_candidates(log2n: int):
+    """(logc, words_per_thread) pairs of the small-batch plans."""
+    out = [(c, 16) for c in candidates(log2n)]
+    out += [(c, 4) for c in candidates(log2n) if 5 <= c <= 12]
+    return out
+
+
+def _graph_us(torch, fn, calls=20, reps=5):
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(calls):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for k in range(reps):
+        g.replay()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) * 1e3 / calls for k in range(reps))
+    del g
+    return per[len(per) // 2]
+
+
+def _calls(lib, name, prm, N, polys, da, db, dc, x, ws):
+    if name == "polymul":
+        return lambda: lib.pm_polymul(da, db, dc, N, 1, polys, prm.q, prm.psi_br, prm.psi_inv_br, ws)
+    if name == "ntt_fwd":
+        return lambda: lib.pm_ntt_fwd(x, N, 1, polys, prm.q, prm.psi_br)
+    return lambda: lib.pm_ntt_inv(x, N, 1, polys, prm.q, prm.psi_inv_br)
+
+
+def tune_small(log2ns, device="cuda", verbose=True):
+    import torch
+    from . import lib, synth
+    lib.load()
+    dev = torch.device(device)
+    lib.pm_tune_set_small_batch(1 << 40)          # every call below is "small" while tuning
+    choices = {k: {} for k in OPS}
+    lat = {k: {} for k in OPS}
+    for log2n in log2ns:
+        if log2n < 5:
+            continue
+        N = 1 << log2n
+        prm = lib.Params(N, 1, device=dev)
+        a, b = synth.operands(synth.SEED_BASE + 18, prm.q, 1, N)
+        da, db = lib.to_device(a, dev), lib.to_device(b, dev)
+        dc = torch.empty_like(da)
+        x = da.clone()
+        for name, op in OPS.items():
+            lat[name][str(log2n)] = {}
+            best, best_us = None, None
+            for logc, wpt in small_candidates(log2n):
+                lib.pm_tune_set_small(op, log2n, logc, wpt)
+                nbytes = lib.pm_polymul_workspace_bytes(N, 1, 1)
+                ws = torch.empty(max(nbytes // 8, 1), dtype=torch.int64, device=dev)
+                us = _graph_us(torch, _calls(lib, name, prm, N, 1, da, db, dc, x, ws))
+                lat[name][str(log2n)]["%d/%d" % (logc, wpt)] = round(us, 2)
+                if best_us is None or us < best_us:
+                    best, best_us = (logc, wpt), us
+            lib.pm_tune_set_small(op, log2n, *best)
+            choices[name][str(log2n)] = list(best)
+            if verbose:
+                print("[tune-small] %-8s N=2^%-2d -> %s  %.2f us  %s" % (name, log2n, best, best_us,
+                                                                    lat[name][str(log2n)]), flush=True)
+    # crossover: the largest batch at which the small plan still wins (forward NTT and product)
+    cross = {}
+    max_words = None
+    for log2n in (12, 16):
+        if str(log2n) not in choices["polymul"]:
+            continue
+        N = 1 << log2n
+        prm = lib.Params(N, 1, device=dev)
+        for name in ("ntt_fwd", "polymul"):
+            op = OPS[name]
+            keep = lib.pm_tune_get_small(op, log2n)
+            won = 0
+            for lp in range(0, 9):
+                polys = 1 << lp
+                a, b = synth.operands(synth.SEED_BASE + 19, prm.q, polys, N)
+                da, db = lib.to_device(a, dev), lib.to_device(b, dev)
+                dc = torch.empty_like(da)
+                x = da.clone()
+                t = {}
+                for label, plan in (("small", keep), ("throughput", (0, 0))):
+                    lib.pm_tune_set_small(op, log2n, *plan)
+                    nbytes = lib.pm_polymul_workspace_bytes(N, 1, polys)
+                    ws = torch.empty(max(nbytes // 8, 1), dtype=torch.int64, device=dev)
+                    t[label] = round(_graph_us(torch, _calls(lib, name, prm, N, polys, da, db, dc, x, ws)), 2)
+                lib.pm_tune_set_small(op, log2n, *keep)
+                cross["%s/%d/%d" % (name, log2n, polys)] = t
+                if t["small"] < t["throughput"]:
+                    won = N * polys
+            max_words = won if max_words is None else min(max_words, won)
+            if verbose:
+                print("[tune-small] crossover %s N=2^%d: small wins up to %d words" % (name, log2n, won), flush=True)
+    max_words = max_words or 0
+    lib.pm_tune_set_small_batch(max_words)
+    return {"max_words": max_words, "choices": choices, "latency_us": lat, "crossover_us": cross}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_DB)
     ap.add_argument("--log2n", default="1-17", help="range lo-hi of log2 N")
+    ap.add_argument("--small", action="store_true",
+                    help="tune only the small-batch plans and merge them into --out")
     a = ap.parse_args()
     lo, hi = (int(v) for v in a.log2n.split("-"))
+    if a.small:
+        db = json.load(open(a.out)) if os.path.exists(a.out) else {}
+        db["small"] = tune_small(range(lo, hi + 1))
+        with open(a.out, "w") as f:
+            json.dump(db, f, indent=1)
+        print("[tune] wrote " + a.out, flush=True)
+        return
     db = tune(range(lo, hi + 1))
+    if os.path.exists(a.out):
+        old = json.load(open(a.out))
+        if "small" in old:
+            db["small"] = old["small"]          # the small-batch plans are tuned separately
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(db, f, indent=1)

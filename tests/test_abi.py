@@ -119,9 +119,20 @@ def test_tune_db_applies(L, tmp_path):
         for name, table in shipped["choices"].items():
             for log2n, logc in table.items():
                 assert logc in tune.candidates(int(log2n))
+        for name, table in shipped["small"]["choices"].items():
+            for log2n, plan in table.items():
+                assert tuple(plan) in tune.small_candidates(int(log2n))
+        n = L.apply_tune_db()
+        assert n == sum(len(t) for t in shipped["choices"].values()) + \
+            sum(len(t) for t in shipped["small"]["choices"].values())
+        assert L.pm_tune_get_small_batch() == shipped["small"]["max_words"] > 0
+        assert L.pm_tune_get_small(L.OP_POLYMUL, 16) == tuple(shipped["small"]["choices"]["polymul"]["16"])
     finally:
-        L.pm_tune_set(L.OP_POLYMUL, 15, 0)
-        L.pm_tune_set(L.OP_NTT_FWD, 13, 0)
+        for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
+            for n in range(1, 18):
+                L.pm_tune_set(op, n, 0)
+                L.pm_tune_set_small(op, n, 0, 0)
+        L.pm_tune_set_small_batch(0)
 
 
 def test_u32_invalid_arguments_rejected_on_host(L):
@@ -177,3 +188,29 @@ def test_il_invalid_arguments_and_workspace(L):
     assert lib.pm_polymul_il(FAKE, ctypes.c_void_p(0x20000), FAKE, 1024, 1, 1, q, FAKE, FAKE, None,
                              None) == L.PM_EINVAL
     assert "workspace" in lib.pm_last_error().decode()
+
+
+def test_small_plan_table(L):
+    lib = L.load()
+    try:
+        assert L.pm_tune_get_small(L.OP_NTT_FWD, 14) == (0, 0)
+        assert L.pm_tune_get_small_batch() == 0
+        L.pm_tune_set_small(L.OP_NTT_FWD, 14, 10, 4)
+        assert L.pm_tune_get_small(L.OP_NTT_FWD, 14) == (10, 4)
+        L.pm_tune_set_small(L.OP_POLYMUL, 13, 13, 16)
+        assert L.pm_tune_get_small(L.OP_POLYMUL, 13) == (13, 16)
+        # 4 words per thread: rows of 2^5..2^12 only; the usual split limits still hold
+        for bad in [(14, 14, 4), (4, 4, 4), (16, 10, 4), (12, 7, 16), (10, 10, 8)]:
+            assert lib.pm_tune_set_small(L.OP_NTT_FWD, *bad) == L.PM_EINVAL, bad
+        # a small plan changes the workspace only for batches under the threshold
+        N = 1 << 13
+        L.pm_tune_set_small(L.OP_POLYMUL, 13, 9, 4)
+        assert L.pm_polymul_workspace_bytes(N, 1, 1) == 0
+        L.pm_tune_set_small_batch(N)
+        assert L.pm_polymul_workspace_bytes(N, 1, 1) == N * 8
+        assert L.pm_polymul_workspace_bytes(N, 1, 2) == 0
+    finally:
+        for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
+            for n in range(1, 18):
+                L.pm_tune_set_small(op, n, 0, 0)
+        L.pm_tune_set_small_batch(0)

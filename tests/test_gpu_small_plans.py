@@ -1,0 +1,153 @@
+"""Small-batch pass plans (4 words per thread in the row pass, shorter rows):
+bit-exact parity with the CPU oracle for every valid (N, row length) under the
+4-word geometry, on 64- and 32-bit words, and the threshold that selects them
+(checked through the names of the kernels the library launched)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import first_mismatch, operands, oracle_ntt_fwd, oracle_ntt_inv, oracle_polymul, oracle_tables
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2209_01290_amd import lib
+    lib.load()
+    return lib
+
+
+@pytest.fixture
+def small(L):
+    """Clears every small-batch plan and the threshold after the test."""
+    yield
+    for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
+        for n in range(1, 18):
+            L.pm_tune_set_small(op, n, 0, 0)
+    L.pm_tune_set_small_batch(0)
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _eq(got, want, what):
+    msg = first_mismatch(np.asarray(got, dtype=np.uint64), np.asarray(want, dtype=np.uint64))
+    assert msg is None, "%s: %s" % (what, msg)
+
+
+def small_plans():
+    out = []
+    for log2n in range(5, 18):
+        for logc in range(5, min(log2n, 12) + 1):
+            if log2n - logc > 5 or (logc < log2n and logc < 8):
+                continue
+            out.append((log2n, logc))
+    return out
+
+
+def _install(L, log2n, logc, wpt=4):
+    for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
+        L.pm_tune_set_small(op, log2n, logc, wpt)
+    L.pm_tune_set_small_batch(1 << 22)
+
+
+def _ws(L, N, limbs, polys, u32=False):
+    import torch
+    n = (L.pm_polymul_u32_workspace_bytes if u32 else L.pm_polymul_workspace_bytes)(N, limbs, polys)
+    return torch.empty(max(n // 8, 1), dtype=torch.int64, device="cuda") if n else None
+
+
+@pytest.mark.parametrize("log2n,logc", small_plans(), ids=lambda v: str(v))
+def test_small_plan_u64(L, small, log2n, logc):
+    import torch
+    N, limbs, polys = 1 << log2n, 2, 2
+    _install(L, log2n, logc)
+    qs = L.pm_ntt_primes(N, limbs)
+    fw_o, iv_o = oracle_tables(qs, N)
+    prm = L.Params(N, limbs, primes=qs)
+    a, b = operands(N, qs, polys, request=1500 + 20 * log2n + logc)
+    L.pm_prof_read(reset=True)
+    L.pm_prof_enable(True)
+    try:
+        x = L.to_device(a)
+        L.pm_ntt_fwd(x, N, limbs, polys, qs, prm.psi_br)
+        _sync()
+        _eq(L.to_host(x).reshape(a.shape), oracle_ntt_fwd(a, qs, fw_o), "fwd N=%d c=%d" % (N, logc))
+        y = L.to_device(a)
+        L.pm_ntt_inv(y, N, limbs, polys, qs, prm.psi_inv_br)
+        _sync()
+        _eq(L.to_host(y).reshape(a.shape), oracle_ntt_inv(a, qs, iv_o), "inv N=%d c=%d" % (N, logc))
+        da, db = L.to_device(a), L.to_device(b)
+        dc = torch.empty_like(da)
+        L.pm_polymul(da, db, dc, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, _ws(L, N, limbs, polys))
+        _sync()
+        want = oracle_polymul(a, b, qs, N, fw_o, iv_o)
+        _eq(L.to_host(dc).reshape(a.shape), want, "polymul N=%d c=%d" % (N, logc))
+        # a = b (the 4-word geometry runs the product with b = a) and c = a
+        L.pm_polymul(da, da, da, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, None)
+        _sync()
+        _eq(L.to_host(da).reshape(a.shape), oracle_polymul(a, a, qs, N, fw_o, iv_o), "square N=%d c=%d" % (N, logc))
+        # the fused product keeps the 16-word rows under the same split
+        df = torch.empty_like(db)
+        L.pm_polymul_fused(L.to_device(a), db, df, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br,
+                           _ws(L, N, limbs, polys))
+        _sync()
+        _eq(L.to_host(df).reshape(a.shape), want, "fused N=%d c=%d" % (N, logc))
+    finally:
+        L.pm_prof_enable(False)
+    names = L.pm_prof_read(reset=True)
+    assert "row_fwd_c%ds" % logc in names and "row_mul_c%ds" % logc in names, sorted(names)
+    assert "row_fmul_c%d" % logc in names
+
+
+@pytest.mark.parametrize("log2n,logc", [p for p in small_plans() if p[0] in (10, 12, 14, 16, 17)],
+                         ids=lambda v: str(v))
+def test_small_plan_u32(L, small, log2n, logc):
+    import torch
+    N, limbs, polys = 1 << log2n, 2, 2
+    _install(L, log2n, logc)
+    qs = L.pm_ntt_primes(N, limbs, 30)
+    fw_o, iv_o = oracle_tables(qs, N)
+    prm = L.Params32(N, limbs, primes=qs)
+    a, b = operands(N, qs, polys, request=1600 + 20 * log2n + logc)
+    x = L.to_device32(a)
+    L.pm_ntt_fwd_u32(x, N, limbs, polys, qs, prm.psi_br)
+    _sync()
+    _eq(L.to_host32(x).reshape(a.shape), oracle_ntt_fwd(a, qs, fw_o), "fwd32 N=%d c=%d" % (N, logc))
+    L.pm_ntt_inv_u32(x, N, limbs, polys, qs, prm.psi_inv_br)
+    _sync()
+    _eq(L.to_host32(x).reshape(a.shape), a, "roundtrip32 N=%d c=%d" % (N, logc))
+    da, db = L.to_device32(a), L.to_device32(b)
+    dc = torch.empty_like(da)
+    L.pm_polymul_u32(da, db, dc, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, _ws(L, N, limbs, polys, True))
+    _sync()
+    _eq(L.to_host32(dc).reshape(a.shape), oracle_polymul(a, b, qs, N, fw_o, iv_o), "polymul32 N=%d c=%d" % (N, logc))
+
+
+def test_threshold_selects_plan(L, small):
+    """Above the threshold the throughput plan runs; at or below it, the small plan."""
+    import torch
+    N, limbs = 1 << 12, 1
+    qs = L.pm_ntt_primes(N, limbs)
+    prm = L.Params(N, limbs, primes=qs)
+    _install(L, 12, 12)
+    L.pm_tune_set_small_batch(4 * N)
+    a, _ = operands(N, qs, 8, request=1700)
+    fw_o, _ = oracle_tables(qs, N)
+    want = oracle_ntt_fwd(a, qs, fw_o)
+    for polys, suffix in ((4, "s"), (8, "")):
+        x = L.to_device(np.ascontiguousarray(a[:, :polys]))
+        L.pm_prof_read(reset=True)
+        L.pm_prof_enable(True)
+        L.pm_ntt_fwd(x, N, limbs, polys, qs, prm.psi_br)
+        L.pm_prof_enable(False)
+        _sync()
+        names = L.pm_prof_read(reset=True)
+        assert list(names) == ["row_fwd_c12" + suffix], names
+        _eq(L.to_host(x).reshape(1, polys, N), want[:, :polys], "threshold polys=%d" % polys)
+    assert L.pm_tune_get_small(L.OP_NTT_FWD, 12) == (12, 4)
+    assert L.pm_tune_get_small_batch() == 4 * N
