@@ -25,7 +25,8 @@
 //     c*mu*2^(61-m) / 2^64 = c*mu / 2^(m+3). For m = 62 the host stores
 //     mu' = mu and the high word is shifted right once more.
 //   * r = x - quot*q is formed modulo 2^64 as x + quot*(2^64 - q); Alg. 4
-//     guarantees 0 <= r < 2q < 2^63, so the correction tests the sign of r-q.
+//     guarantees 0 <= r < 2q, so one subtraction of q, kept unless it
+//     borrows, makes r canonical.
 //
 // Two instantiations:
 //   KIND_WIDE  every modulus of the launch has 34 <= m <= 61 (all 60-bit NTT
@@ -54,17 +55,30 @@ enum { KIND_WIDE = 0, KIND_ANY = 1 };
 __device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
 __device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
 
-// (a + b) mod q: s - q is negative exactly when s < q (|s - q| < 2^63).
-__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) {
-  const uint64_t s = a + b;
-  const uint64_t d = s - q;
-  return ((int64_t)d < 0) ? s : d;
+__device__ __forceinline__ uint64_t pack64(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+
+// The single correctional subtraction: s - q unless that borrows (s < q).
+// The select reads the borrow of the 64-bit subtraction itself, so no
+// separate comparison is issued.
+__device__ __forceinline__ uint64_t csub(uint64_t s, uint64_t q) {
+  unsigned b0, b1;
+  const uint32_t d0 = __builtin_subc(lo32(s), lo32(q), 0u, &b0);
+  const uint32_t d1 = __builtin_subc(hi32(s), hi32(q), b0, &b1);
+  return b1 ? s : pack64(d0, d1);
 }
 
-// (a - b) mod q
+// (a + b) mod q (Alg. 1): a + b < 2q, one correctional subtraction.
+__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) {
+  return csub(a + b, q);
+}
+
+// (a - b) mod q: plus q when the subtraction borrows (a < b).
 __device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) {
-  const uint64_t d = a - b;
-  return ((int64_t)d < 0) ? d + q : d;
+  unsigned b0, b1;
+  const uint32_t d0 = __builtin_subc(lo32(a), lo32(b), 0u, &b0);
+  const uint32_t d1 = __builtin_subc(hi32(a), hi32(b), b0, &b1);
+  const uint64_t d = pack64(d0, d1);
+  return b1 ? d + q : d;
 }
 
 // x/2 mod q for x in [0, q), q odd.
@@ -110,8 +124,7 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Mod& M)
   const uint32_t k0 = lo32(quot), k1 = hi32(quot);
   uint64_t r = (uint64_t)k0 * lo32(nq) + (((uint64_t)x1 << 32) | x0);
   r += (uint64_t)(k0 * hi32(nq) + k1 * lo32(nq)) << 32;
-  const uint64_t d = r - M.q;
-  return ((int64_t)d < 0) ? r : d;
+  return csub(r, M.q);
 }
 
 // CT butterfly of the merged forward NTT (Alg. 5):
