@@ -517,24 +517,35 @@ def main():
                         "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
                         "what": "384 separate pm_polymul calls per step (one launch sequence each)"}
         out["batched_over_plain"] = round(value / out["plain"]["value"], 3)
-        # the fused product of Sec. III-B (Alg. 8) on the same batch
+        # the fused product of Sec. III-B (Alg. 8) on the same batch, in
+        # alternating blocks of 10 steps with the Eq. 2 step (same clocks)
         def fstep():
             lib.pm_polymul_fused(da, db, dc, N, LIMBS, POLYS, qs, prm.psi_br, prm.psi_inv_br, ws)
-        for _ in range(3):
-            fstep()
+        blocks = {"eq2": [], "fused": []}
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(4):
+            for name, fn in (("eq2", step), ("fused", fstep)):
+                for _ in range(2):
+                    fn()
+                e0.record(stream)
+                for _ in range(10):
+                    fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                blocks[name].append(e0.elapsed_time(e1) / 10)
         lib.pm_prof_read(reset=True)
         lib.pm_prof_enable(True)
-        e0.record(stream)
-        reps = 20
-        for _ in range(reps):
+        for _ in range(10):
             fstep()
-        e1.record(stream)
         torch.cuda.synchronize()
         lib.pm_prof_enable(False)
         fk = lib.pm_prof_read(reset=True)
-        out["fused"] = {"value": round(products * reps / (e0.elapsed_time(e1) / 1e3), 1), "unit": "polymul/s",
-                        "what": "pm_polymul_fused (Alg. 8: truncated NTTs + Karatsuba-fused Hadamard)",
+        f_ms, q_ms = pct(blocks["fused"], 50), pct(blocks["eq2"], 50)
+        out["fused"] = {"value": round(products / f_ms * 1e3, 1), "unit": "polymul/s",
+                        "ms_per_step": round(f_ms, 4), "eq2_ms_per_step_alternating": round(q_ms, 4),
+                        "fused_over_eq2": round(q_ms / f_ms, 4),
+                        "what": "pm_polymul_fused (Alg. 8: truncated NTTs + Karatsuba-fused Hadamard), "
+                                "median of 4 blocks of 10 steps alternating with the Eq. 2 step",
                         "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(fk.items())}}
         # stagewise: one launch per NTT stage, whole batch per launch
         sws = torch.empty(lib.pm_polymul_stagewise_workspace_bytes(N, LIMBS, POLYS) // 8,

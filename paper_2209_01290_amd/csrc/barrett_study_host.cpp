@@ -5,10 +5,10 @@
 #include <string>
 
 #include "../../include/pm.h"
+#include "pm_host.hpp"
 #include "pm_internal.hpp"
 
 namespace pm {
-int set_error(int code, const std::string& msg);
 
 // mu of each variant: floor(2^(2m)/q) (Alg. 2), floor(2^(2m+3)/q) (Alg. 3),
 // floor(2^(2m+1)/q) (Alg. 4); word-size limits as the paper states them:

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/pm.h"
+#include "pm_host.hpp"
 #include "pm_internal.hpp"
 #include "pm_plan.hpp"
 #include "pm_prof.hpp"
@@ -34,7 +35,6 @@ typedef unsigned __int128 u128;
 
 bool is_pow2(size_t n) { return n && !(n & (n - 1)); }
 unsigned log2u(size_t n) { unsigned l = 0; while (((size_t)1 << l) < n) ++l; return l; }
-bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
 }  // namespace
 
@@ -98,14 +98,30 @@ int mod_kind32(const Mod32& M) { return M.t ? KIND_ANY : KIND_WIDE; }
 
 namespace {
 
-struct Batch {
+// Per-word-type pieces: modulus limits and constants, kernel-name tag.
+template <typename W> struct Word;
+template <> struct Word<uint64_t> {
+  static constexpr const char* q_rule = "q must be odd with 3 <= q < 2^62";
+  static bool make(uint64_t q, Mod* M) { return (q & 1) && q >= 3 && !(q >> 62) && make_mod(q, M); }
+  static int kind(const Mod& M) { return mod_kind(M); }
+};
+template <> struct Word<uint32_t> {
+  static constexpr const char* q_rule = "q must be odd with 3 <= q < 2^30";
+  static bool make(uint32_t q, Mod32* M) { return make_mod32(q, M); }
+  static int kind(const Mod32& M) { return mod_kind32(M); }
+};
+
+// A validated batch: sizes, the per-limb constants, the instantiation kind.
+template <typename W>
+struct BatchT {
   size_t N, limbs, polys;
   unsigned log2n;
-  std::vector<Mod> mods;
+  std::vector<typename ModOf<W>::type> mods;
   int kind;
 };
 
-int check_batch(Batch* b, size_t N, size_t limbs, size_t polys, const uint64_t* q) {
+template <typename W>
+int check_batch(BatchT<W>* b, size_t N, size_t limbs, size_t polys, const W* q) {
   if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N))
     return fail(PM_EINVAL, "N must be a power of two in [2, 2^17], got " + std::to_string(N));
   if (limbs == 0 || polys == 0) return fail(PM_EINVAL, "limbs and polys_per_limb must be positive");
@@ -115,55 +131,63 @@ int check_batch(Batch* b, size_t N, size_t limbs, size_t polys, const uint64_t* 
   b->mods.resize(limbs);
   b->kind = KIND_WIDE;
   for (size_t l = 0; l < limbs; ++l) {
-    const uint64_t ql = q[l];
-    if (!(ql & 1) || ql < 3 || (ql >> 62))
-      return fail(PM_EINVAL, "limb " + std::to_string(l) + ": q must be odd with 3 <= q < 2^62");
+    const W ql = q[l];
+    if (!Word<W>::make(ql, &b->mods[l]))
+      return fail(PM_EINVAL, "limb " + std::to_string(l) + ": " + Word<W>::q_rule);
     if ((ql - 1) % (2 * (uint64_t)N) != 0)
       return fail(PM_EINVAL, "limb " + std::to_string(l) + ": 2N must divide q - 1");
-    make_mod(ql, &b->mods[l]);
-    if (mod_kind(b->mods[l]) != KIND_WIDE) b->kind = KIND_ANY;
+    if (Word<W>::kind(b->mods[l]) != KIND_WIDE) b->kind = KIND_ANY;
   }
   return PM_OK;
 }
 
+// Device pointers must be non-null and aligned to their word size.
+template <typename W = uint64_t>
 int check_ptr(const void* p, const char* name) {
   if (!p) return fail(PM_EINVAL, std::string(name) + " is null");
-  if (!aligned8(p)) return fail(PM_EINVAL, std::string(name) + " is not 8-byte aligned");
+  if ((uintptr_t)p & (sizeof(W) - 1))
+    return fail(PM_EINVAL, std::string(name) + " is not " + std::to_string(sizeof(W)) + "-byte aligned");
   return PM_OK;
 }
 
-// Launch wrappers that name each kernel for the event timer.
-// Row kernel names: row_<mode>_c<logc>, with a trailing "s" for the
-// small-batch geometry (4 words per thread).
-const char* row_name(int mode, int logc, int ebx = 4) {
-  static std::vector<std::string> names = [] {
+// Launch wrappers that name each kernel for the event timer:
+// row[32]_<mode>_c<logc>, with a trailing "s" for the small-batch geometry
+// (4 words per thread), and col[32]_<fwd|inv>_r<logr>.
+template <typename W>
+const char* row_name(int mode, int logc, int ebx) {
+  static const std::vector<std::string> names = [] {
+    const std::string tag = sizeof(W) == 4 ? "row32_" : "row_";
+    const char* m[5] = {"fwd_c", "inv_c", "mul_c", "sqr_c", "fmul_c"};
     std::vector<std::string> v;
-    const char* m[5] = {"row_fwd_c", "row_inv_c", "row_mul_c", "row_sqr_c", "row_fmul_c"};
     for (int g = 0; g < 2; ++g)
       for (int i = 0; i < 5; ++i)
-        for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c) + (g ? "s" : ""));
+        for (int c = 0; c <= 14; ++c) v.push_back(tag + m[i] + std::to_string(c) + (g ? "s" : ""));
     return v;
   }();
   return names[(ebx == 2 ? 75 : 0) + mode * 15 + logc].c_str();
 }
 
+template <typename W>
 const char* col_name(bool inv, int logr) {
-  static std::vector<std::string> names = [] {
+  static const std::vector<std::string> names = [] {
+    const std::string tag = sizeof(W) == 4 ? "col32_" : "col_";
     std::vector<std::string> v;
     for (int i = 0; i < 2; ++i)
-      for (int r = 0; r <= 5; ++r) v.push_back(std::string(i ? "col_inv_r" : "col_fwd_r") + std::to_string(r));
+      for (int r = 0; r <= 5; ++r) v.push_back(tag + (i ? "inv_r" : "fwd_r") + std::to_string(r));
     return v;
   }();
   return names[(inv ? 6 : 0) + logr].c_str();
 }
 
-hipError_t run_row(int logc, int kind, int mode, const RowArgs& a, hipStream_t s, int ebx = 4) {
-  ProfScope ps(s, row_name(mode, logc, ebx));
+template <typename W>
+hipError_t run_row(int logc, int kind, int mode, const RowArgsT<W>& a, hipStream_t s, int ebx = 4) {
+  ProfScope ps(s, row_name<W>(mode, logc, ebx));
   return launch_row(logc, kind, mode, a, s, ebx);
 }
 
-hipError_t run_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_t s) {
-  ProfScope ps(s, col_name(inv, logr));
+template <typename W>
+hipError_t run_col(int logr, int kind, bool inv, const ColArgsT<W>& a, hipStream_t s) {
+  ProfScope ps(s, col_name<W>(inv, logr));
   return launch_col(logr, kind, inv, a, s);
 }
 
@@ -178,10 +202,10 @@ hipError_t run_pointwise(int kind, const uint64_t* A, const uint64_t* B, uint64_
   return launch_pointwise(kind, A, B, C, log2n, polys, limbs, ls, s);
 }
 
-// Calls f(limb0, nlimbs, LimbSet) for consecutive chunks of at most MAXL limbs.
-template <class F>
-int for_chunks(const Batch& b, F f) {
-  LimbSet ls;
+// Calls f(limb0, nlimbs, LimbSetT<W>) for consecutive chunks of at most MAXL limbs.
+template <typename W, class F>
+int for_chunks(const BatchT<W>& b, F f) {
+  LimbSetT<W> ls;
   for (size_t l0 = 0; l0 < b.limbs; l0 += MAXL) {
     const size_t nl = std::min((size_t)MAXL, b.limbs - l0);
     std::memset(&ls, 0, sizeof(ls));
@@ -192,83 +216,93 @@ int for_chunks(const Batch& b, F f) {
   return PM_OK;
 }
 
-// ---- 32-bit words
-struct Batch32 {
-  size_t N, limbs, polys;
-  unsigned log2n;
-  std::vector<Mod32> mods;
-  int kind;
-};
-
-int check_batch32(Batch32* b, size_t N, size_t limbs, size_t polys, const uint32_t* q) {
-  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N))
-    return fail(PM_EINVAL, "N must be a power of two in [2, 2^17], got " + std::to_string(N));
-  if (limbs == 0 || polys == 0) return fail(PM_EINVAL, "limbs and polys_per_limb must be positive");
-  if (polys > 65535) return fail(PM_EINVAL, "polys_per_limb above 65535 is not supported");
-  if (!q) return fail(PM_EINVAL, "q (host array of limbs moduli) is null");
-  b->N = N; b->limbs = limbs; b->polys = polys; b->log2n = log2u(N);
-  b->mods.resize(limbs);
-  b->kind = KIND_WIDE;
-  for (size_t l = 0; l < limbs; ++l) {
-    const uint32_t ql = q[l];
-    if (!make_mod32(ql, &b->mods[l]))
-      return fail(PM_EINVAL, "limb " + std::to_string(l) + ": q must be odd with 3 <= q < 2^30");
-    if ((ql - 1) % (2 * (uint64_t)N) != 0)
-      return fail(PM_EINVAL, "limb " + std::to_string(l) + ": 2N must divide q - 1");
-    if (mod_kind32(b->mods[l]) != KIND_WIDE) b->kind = KIND_ANY;
-  }
-  return PM_OK;
+// The merged transforms (Alg. 5 / Alg. 6 halved) over a batch, in place.
+template <typename W>
+int ntt_common(W* x, size_t N, size_t limbs, size_t polys, const W* q, const W* tw, pm_stream_t stream, bool inv) {
+  BatchT<W> b;
+  int rc;
+  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr<W>(x, "x")) || (rc = check_ptr<W>(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
+  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n, N * limbs * polys);
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSetT<W>& ls) -> hipError_t {
+    W* xs = x + l0 * polys * N;
+    const W* t = tw + l0 * N;
+    RowArgsT<W> ra{xs, nullptr, xs, inv ? nullptr : t, inv ? t : nullptr, b.log2n, p.R, (uint32_t)polys,
+                   (uint32_t)nl, &ls};
+    ColArgsT<W> ca{xs, xs, nullptr, nullptr, t, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+    hipError_t e;
+    if (!inv) {
+      if (p.R > 1 && (e = run_col(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
+      return run_row(p.logc, b.kind, ROW_FWD, ra, s, p.ebx);
+    }
+    if ((e = run_row(p.logc, b.kind, ROW_INV, ra, s, p.ebx)) != hipSuccess) return e;
+    if (p.R > 1) return run_col(p.logr, b.kind, true, ca, s);
+    return hipSuccess;
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
 }
 
-int check_ptr32(const void* p, const char* name) {
-  if (!p) return fail(PM_EINVAL, std::string(name) + " is null");
-  if ((uintptr_t)p & 3u) return fail(PM_EINVAL, std::string(name) + " is not 4-byte aligned");
-  return PM_OK;
+template <typename W>
+size_t polymul_workspace(size_t N, size_t limbs, size_t polys) {
+  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N)) return 0;
+  const PassPlan p = plan_for(OP_POLYMUL, log2u(N), N * limbs * polys);
+  return p.R > 1 ? N * limbs * polys * sizeof(W) : 0;
 }
 
-const char* row_name32(int mode, int logc, int ebx = 4) {
-  static std::vector<std::string> names = [] {
-    std::vector<std::string> v;
-    const char* m[3] = {"row32_fwd_c", "row32_inv_c", "row32_mul_c"};
-    for (int g = 0; g < 2; ++g)
-      for (int i = 0; i < 3; ++i)
-        for (int c = 0; c <= 14; ++c) v.push_back(std::string(m[i]) + std::to_string(c) + (g ? "s" : ""));
-    return v;
-  }();
-  return names[(ebx == 2 ? 45 : 0) + mode * 15 + logc].c_str();
-}
-
-const char* col_name32(bool inv, int logr) {
-  static std::vector<std::string> names = [] {
-    std::vector<std::string> v;
-    for (int i = 0; i < 2; ++i)
-      for (int r = 0; r <= 5; ++r) v.push_back(std::string(i ? "col32_inv_r" : "col32_fwd_r") + std::to_string(r));
-    return v;
-  }();
-  return names[(inv ? 6 : 0) + logr].c_str();
-}
-
-hipError_t run_row32(int logc, int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s, int ebx = 4) {
-  ProfScope ps(s, row_name32(mode, logc, ebx));
-  return launch_row(logc, kind, mode, a, s, ebx);
-}
-
-hipError_t run_col32(int logr, int kind, bool inv, const ColArgsT<uint32_t>& a, hipStream_t s) {
-  ProfScope ps(s, col_name32(inv, logr));
-  return launch_col(logr, kind, inv, a, s);
-}
-
-template <class F>
-int for_chunks32(const Batch32& b, F f) {
-  LimbSet32 ls;
-  for (size_t l0 = 0; l0 < b.limbs; l0 += MAXL) {
-    const size_t nl = std::min((size_t)MAXL, b.limbs - l0);
-    std::memset(&ls, 0, sizeof(ls));
-    for (size_t i = 0; i < nl; ++i) ls.mod[i] = b.mods[l0 + i];
-    hipError_t e = f(l0, nl, ls);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-  }
-  return PM_OK;
+// Eq. 2 over a batch (fused: Alg. 8's rows instead of the pointwise rows).
+// 32-bit words have neither the squaring nor the fused row kernels.
+template <typename W>
+int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t polys, const W* q,
+                   const W* psi_br, const W* psi_inv_br, void* workspace, pm_stream_t stream, bool fused) {
+  constexpr bool W64 = sizeof(W) == 8;
+  BatchT<W> b;
+  int rc;
+  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
+  if ((rc = check_ptr<W>(a, "a")) || (rc = check_ptr<W>(b_, "b")) || (rc = check_ptr<W>(c, "c")) ||
+      (rc = check_ptr<W>(psi_br, "psi_br")) || (rc = check_ptr<W>(psi_inv_br, "psi_inv_br")))
+    return rc;
+  const PassPlan p = plan_for(OP_POLYMUL, b.log2n, N * limbs * polys);
+  // the fused product needs N >= 4 (Alg. 8's squared-twiddle identity)
+  fused = W64 && fused && b.log2n >= 2;
+  const bool same = (a == b_);          // one operand: one column pass, no workspace
+  // and, unfused, one row transform (the small-batch geometry has no squaring
+  // mode: it runs the product with b = a)
+  const bool square = W64 && same && !fused && p.ebx == 4;
+  // the fused rows exist in the 16-word geometry only
+  const int ebx = fused ? 4 : (int)p.ebx;
+  const int mode = fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL);
+  // The product is commutative: when c aliases b, swap so that c aliases a.
+  const W* A = a;
+  const W* B = b_;
+  if (c == B && c != A) std::swap(A, B);
+  if (p.R > 1 && !same && (rc = check_ptr<W>(workspace, "workspace"))) return rc;
+  W* ws = (W*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSetT<W>& ls) -> hipError_t {
+    const size_t base = l0 * polys * N;
+    const W* tf = psi_br + l0 * N;
+    const W* ti = psi_inv_br + l0 * N;
+    if (p.R == 1) {
+      RowArgsT<W> ra{A + base, square ? nullptr : B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys,
+                     (uint32_t)nl, &ls};
+      return run_row(p.logc, b.kind, mode, ra, s, ebx);
+    }
+    // column stages of a (-> c) and b (-> workspace), fused rows, inverse columns of c
+    W* wb = same ? c + base : ws + base;
+    ColArgsT<W> cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
+                   same ? 1u : 2u, &ls};
+    hipError_t e = run_col(p.logr, b.kind, false, cf, s);
+    if (e != hipSuccess) return e;
+    RowArgsT<W> ra{c + base, square ? nullptr : wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys,
+                   (uint32_t)nl, &ls};
+    if ((e = run_row(p.logc, b.kind, mode, ra, s, ebx)) != hipSuccess) return e;
+    ColArgsT<W> ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
+    return run_col(p.logr, b.kind, true, ci, s);
+  });
+  if (rc == PM_OK) g_err.clear();
+  return rc;
 }
 
 }  // namespace
@@ -296,34 +330,6 @@ int pm_barrett_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t 
   return PM_OK;
 }
 
-static int ntt_common(uint64_t* x, size_t N, size_t limbs, size_t polys, const uint64_t* q,
-                      const uint64_t* tw, pm_stream_t stream, bool inv) {
-  Batch b;
-  int rc;
-  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
-  if ((rc = check_ptr(x, "x")) || (rc = check_ptr(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
-  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n, N * limbs * polys);
-  hipStream_t s = (hipStream_t)stream;
-  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
-    const size_t base = l0 * polys * N;
-    uint64_t* xs = x + base;
-    const uint64_t* t = tw + l0 * N;
-    RowArgs ra{xs, nullptr, xs, inv ? nullptr : t, inv ? t : nullptr, b.log2n, p.R, (uint32_t)polys,
-               (uint32_t)nl, &ls};
-    ColArgs ca{xs, xs, nullptr, nullptr, t, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
-    hipError_t e;
-    if (!inv) {
-      if (p.R > 1 && (e = run_col(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
-      return run_row(p.logc, b.kind, ROW_FWD, ra, s, p.ebx);
-    }
-    if ((e = run_row(p.logc, b.kind, ROW_INV, ra, s, p.ebx)) != hipSuccess) return e;
-    if (p.R > 1) return run_col(p.logr, b.kind, true, ca, s);
-    return hipSuccess;
-  });
-  if (rc == PM_OK) g_err.clear();
-  return rc;
-}
-
 int pm_ntt_fwd(uint64_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint64_t* q,
                const uint64_t* psi_br, pm_stream_t stream) {
   return ntt_common(x, N, limbs, polys_per_limb, q, psi_br, stream, false);
@@ -335,63 +341,7 @@ int pm_ntt_inv(uint64_t* x, size_t N, size_t limbs, size_t polys_per_limb, const
 }
 
 size_t pm_polymul_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {
-  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N)) return 0;
-  const PassPlan p = plan_for(OP_POLYMUL, log2u(N), N * limbs * polys_per_limb);
-  return p.R > 1 ? N * limbs * polys_per_limb * sizeof(uint64_t) : 0;
-}
-
-static int polymul_common(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, size_t limbs,
-                          size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br,
-                          const uint64_t* psi_inv_br, void* workspace, pm_stream_t stream, bool fused) {
-  Batch b;
-  int rc;
-  const size_t polys = polys_per_limb;
-  if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
-  if ((rc = check_ptr(a, "a")) || (rc = check_ptr(b_, "b")) || (rc = check_ptr(c, "c")) ||
-      (rc = check_ptr(psi_br, "psi_br")) || (rc = check_ptr(psi_inv_br, "psi_inv_br")))
-    return rc;
-  const PassPlan p = plan_for(OP_POLYMUL, b.log2n, N * limbs * polys);
-  // the fused product needs N >= 4 (Alg. 8's squared-twiddle identity)
-  fused = fused && b.log2n >= 2;
-  const bool same = (a == b_);          // one operand: one column pass, no workspace
-  // and, unfused, one row transform (the small-batch geometry has no squaring
-  // mode: it runs the product with b = a)
-  const bool square = same && !fused && p.ebx == 4;
-  // the fused rows exist in the 16-word geometry only
-  const int ebx = fused ? 4 : (int)p.ebx;
-  // The product is commutative: when c aliases b, swap so that c aliases a.
-  const uint64_t* A = a;
-  const uint64_t* B = b_;
-  if (c == B && c != A) std::swap(A, B);
-  uint64_t* ws = (uint64_t*)workspace;
-  if (p.R > 1 && !same) {
-    if ((rc = check_ptr(workspace, "workspace"))) return rc;
-  }
-  hipStream_t s = (hipStream_t)stream;
-  rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
-    const size_t base = l0 * polys * N;
-    const uint64_t* tf = psi_br + l0 * N;
-    const uint64_t* ti = psi_inv_br + l0 * N;
-    if (p.R == 1) {
-      RowArgs ra{A + base, square ? nullptr : B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys,
-                 (uint32_t)nl, &ls};
-      return run_row(p.logc, b.kind, fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL), ra, s, ebx);
-    }
-    // column stages of a (-> c) and b (-> workspace), fused rows, inverse columns of c
-    uint64_t* wb = same ? c + base : ws + base;
-    ColArgs cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
-               same ? 1u : 2u, &ls};
-    hipError_t e = run_col(p.logr, b.kind, false, cf, s);
-    if (e != hipSuccess) return e;
-    RowArgs ra{c + base, square ? nullptr : wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl,
-               &ls};
-    if ((e = run_row(p.logc, b.kind, fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL), ra, s, ebx)) != hipSuccess)
-      return e;
-    ColArgs ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
-    return run_col(p.logr, b.kind, true, ci, s);
-  });
-  if (rc == PM_OK) g_err.clear();
-  return rc;
+  return polymul_workspace<uint64_t>(N, limbs, polys_per_limb);
 }
 
 int pm_polymul(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t N, size_t limbs, size_t polys_per_limb,
@@ -413,7 +363,7 @@ size_t pm_polymul_stagewise_workspace_bytes(size_t N, size_t limbs, size_t polys
 int pm_polymul_stagewise(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, size_t limbs,
                          size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br,
                          const uint64_t* psi_inv_br, void* workspace, pm_stream_t stream) {
-  Batch b;
+  BatchT<uint64_t> b;
   int rc;
   const size_t polys = polys_per_limb;
   if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
@@ -455,88 +405,24 @@ int pm_polymul_stagewise(const uint64_t* a, const uint64_t* b_, uint64_t* c, siz
 // The same merged transforms and Eq. 2 product on 32-bit words, for moduli of
 // up to 30 bits (Alg. 4 with beta = 32), with the pass plan of the 64-bit path.
 
-static int ntt_common32(uint32_t* x, size_t N, size_t limbs, size_t polys, const uint32_t* q,
-                        const uint32_t* tw, pm_stream_t stream, bool inv) {
-  Batch32 b;
-  int rc;
-  if ((rc = check_batch32(&b, N, limbs, polys, q))) return rc;
-  if ((rc = check_ptr32(x, "x")) || (rc = check_ptr32(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
-  const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n, N * limbs * polys);
-  hipStream_t s = (hipStream_t)stream;
-  rc = for_chunks32(b, [&](size_t l0, size_t nl, const LimbSet32& ls) -> hipError_t {
-    uint32_t* xs = x + l0 * polys * N;
-    const uint32_t* t = tw + l0 * N;
-    RowArgsT<uint32_t> ra{xs, nullptr, xs, inv ? nullptr : t, inv ? t : nullptr, b.log2n, p.R, (uint32_t)polys,
-                          (uint32_t)nl, &ls};
-    ColArgsT<uint32_t> ca{xs, xs, nullptr, nullptr, t, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
-    hipError_t e;
-    if (!inv) {
-      if (p.R > 1 && (e = run_col32(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
-      return run_row32(p.logc, b.kind, ROW_FWD, ra, s, p.ebx);
-    }
-    if ((e = run_row32(p.logc, b.kind, ROW_INV, ra, s, p.ebx)) != hipSuccess) return e;
-    if (p.R > 1) return run_col32(p.logr, b.kind, true, ca, s);
-    return hipSuccess;
-  });
-  if (rc == PM_OK) g_err.clear();
-  return rc;
-}
-
 int pm_ntt_fwd_u32(uint32_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint32_t* q,
                    const uint32_t* psi_br, pm_stream_t stream) {
-  return ntt_common32(x, N, limbs, polys_per_limb, q, psi_br, stream, false);
+  return ntt_common(x, N, limbs, polys_per_limb, q, psi_br, stream, false);
 }
 
 int pm_ntt_inv_u32(uint32_t* x, size_t N, size_t limbs, size_t polys_per_limb, const uint32_t* q,
                    const uint32_t* psi_inv_br, pm_stream_t stream) {
-  return ntt_common32(x, N, limbs, polys_per_limb, q, psi_inv_br, stream, true);
+  return ntt_common(x, N, limbs, polys_per_limb, q, psi_inv_br, stream, true);
 }
 
 size_t pm_polymul_u32_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb) {
-  if (!is_pow2(N) || N < 2 || N > ((size_t)1 << PM_MAX_LOG2N)) return 0;
-  const PassPlan p = plan_for(OP_POLYMUL, log2u(N), N * limbs * polys_per_limb);
-  return p.R > 1 ? N * limbs * polys_per_limb * sizeof(uint32_t) : 0;
+  return polymul_workspace<uint32_t>(N, limbs, polys_per_limb);
 }
 
-int pm_polymul_u32(const uint32_t* a, const uint32_t* b_, uint32_t* c, size_t N, size_t limbs,
+int pm_polymul_u32(const uint32_t* a, const uint32_t* b, uint32_t* c, size_t N, size_t limbs,
                    size_t polys_per_limb, const uint32_t* q, const uint32_t* psi_br, const uint32_t* psi_inv_br,
                    void* workspace, pm_stream_t stream) {
-  Batch32 b;
-  int rc;
-  const size_t polys = polys_per_limb;
-  if ((rc = check_batch32(&b, N, limbs, polys, q))) return rc;
-  if ((rc = check_ptr32(a, "a")) || (rc = check_ptr32(b_, "b")) || (rc = check_ptr32(c, "c")) ||
-      (rc = check_ptr32(psi_br, "psi_br")) || (rc = check_ptr32(psi_inv_br, "psi_inv_br")))
-    return rc;
-  const PassPlan p = plan_for(OP_POLYMUL, b.log2n, N * limbs * polys);
-  const bool same = (a == b_);          // one operand: one column pass, no workspace
-  const uint32_t* A = a;
-  const uint32_t* B = b_;
-  if (c == B && c != A) std::swap(A, B);
-  if (p.R > 1 && !same && (rc = check_ptr32(workspace, "workspace"))) return rc;
-  uint32_t* ws = (uint32_t*)workspace;
-  hipStream_t s = (hipStream_t)stream;
-  rc = for_chunks32(b, [&](size_t l0, size_t nl, const LimbSet32& ls) -> hipError_t {
-    const size_t base = l0 * polys * N;
-    const uint32_t* tf = psi_br + l0 * N;
-    const uint32_t* ti = psi_inv_br + l0 * N;
-    if (p.R == 1) {
-      RowArgsT<uint32_t> ra{A + base, B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys, (uint32_t)nl, &ls};
-      return run_row32(p.logc, b.kind, ROW_MUL, ra, s, p.ebx);
-    }
-    uint32_t* wb = same ? c + base : ws + base;
-    ColArgsT<uint32_t> cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
-                          same ? 1u : 2u, &ls};
-    hipError_t e = run_col32(p.logr, b.kind, false, cf, s);
-    if (e != hipSuccess) return e;
-    RowArgsT<uint32_t> ra{c + base, wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys, (uint32_t)nl, &ls};
-    if ((e = run_row32(p.logc, b.kind, ROW_MUL, ra, s, p.ebx)) != hipSuccess) return e;
-    ColArgsT<uint32_t> ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1,
-                          &ls};
-    return run_col32(p.logr, b.kind, true, ci, s);
-  });
-  if (rc == PM_OK) g_err.clear();
-  return rc;
+  return polymul_common(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace, stream, false);
 }
 
 // ------------------------------------------------------ interleaved layout --
@@ -574,7 +460,7 @@ static hipError_t run_il(int logr, int kind, int mode, const IlArgs& a, hipStrea
 
 static int ntt_common_il(uint64_t* x, size_t N, size_t limbs, size_t polys, const uint64_t* q,
                          const uint64_t* tw, pm_stream_t stream, bool inv) {
-  Batch b;
+  BatchT<uint64_t> b;
   int rc;
   if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
   if ((rc = check_ptr(x, "x")) || (rc = check_ptr(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
@@ -623,7 +509,7 @@ size_t pm_polymul_il_workspace_bytes(size_t N, size_t limbs, size_t polys_per_li
 int pm_polymul_il(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, size_t limbs,
                   size_t polys_per_limb, const uint64_t* q, const uint64_t* psi_br, const uint64_t* psi_inv_br,
                   void* workspace, pm_stream_t stream) {
-  Batch b;
+  BatchT<uint64_t> b;
   int rc;
   const size_t polys = polys_per_limb;
   if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;

@@ -17,16 +17,11 @@
 #include <vector>
 
 #include "../../include/pm.h"
+#include "pm_host.hpp"
 #include "pm_internal.hpp"
 #include "pm_jobs.hpp"
 #include "pm_plan.hpp"
 #include "pm_prof.hpp"
-
-namespace pm {
-bool make_mod(uint64_t q, Mod* M);
-int mod_kind(const Mod& M);
-int set_error(int code, const std::string& msg);
-}  // namespace pm
 
 using namespace pm;
 

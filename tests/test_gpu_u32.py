@@ -219,3 +219,35 @@ def test_edge_values_u32(L, log2n):
     _eq(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "u32 edges N=%d" % N)
     assert not got[0, 0].any()
     assert np.array_equal(got[0, 3], b[0, 3])
+
+
+def test_words32_full_size(L):
+    """The 32-bit benchmark shape: N = 2^16, 96 limbs of 30-bit primes x 8 pairs
+    (two launches of 64 + 32 limbs), with the packaged pass plans installed;
+    oracle on sampled polynomials (a limb of each launch) and coefficients."""
+    import torch
+    N, limbs, polys = 1 << 16, 96, 8
+    L.apply_tune_db()
+    try:
+        prm = L.Params32(N, limbs, bits=30)
+        qs = prm.q
+        a, b = operands(N, qs, polys, request=2000)
+        da, db = L.to_device32(a), L.to_device32(b)
+        dc = torch.empty_like(da)
+        L.pm_polymul_u32(da, db, dc, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, _ws(L, N, limbs, polys))
+        _sync()
+        got = L.to_host32(dc).reshape(a.shape)
+        o = oracle.default()
+        for l, p in [(0, 0), (63, 5), (64, 2), (95, 7)]:
+            fw, iv = o.psi_tables(qs[l], N)
+            _eq(got[l, p], o.polymul_ntt(a[l, p], b[l, p], qs[l], fw, iv), "words32 (%d,%d)" % (l, p))
+        rng = np.random.default_rng(32)
+        for _ in range(8):
+            l, p, k = int(rng.integers(limbs)), int(rng.integers(polys)), int(rng.integers(N))
+            assert int(got[l, p, k]) == o.polymul_coeff(a[l, p], b[l, p], qs[l], k), (l, p, k)
+    finally:
+        for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
+            for n in range(1, 18):
+                L.pm_tune_set(op, n, 0)
+                L.pm_tune_set_small(op, n, 0, 0)
+        L.pm_tune_set_small_batch(0)
