@@ -140,7 +140,8 @@ size_t pm_polymul_il_workspace_bytes(size_t N, size_t limbs, size_t polys_per_li
 /* --------------------------------------------------------- 32-bit words
  * The paper's 30-bit NTT timings (Sec. VII, comparison table) use 32-bit words:
  * Alg. 4 with beta = 32 needs len(q) <= 30. These calls are pm_ntt_fwd,
- * pm_ntt_inv and pm_polymul on 32-bit words, with the same layouts, aliasing,
+ * pm_ntt_inv, pm_polymul and pm_polymul_fused on 32-bit words (the fused and
+ * squaring rows included), with the same layouts, aliasing,
  * stream and error rules, for moduli q odd with 3 <= q < 2^30 and 2N | q - 1.
  * x, a, b, c, psi_br, psi_inv_br: device arrays of uint32_t, 4-byte aligned;
  * q: host array of limbs moduli. pm_make_tables_u32 writes the twiddle tables
@@ -153,6 +154,10 @@ int pm_ntt_inv_u32(uint32_t *x, size_t N, size_t limbs, size_t polys_per_limb, c
 int pm_polymul_u32(const uint32_t *a, const uint32_t *b, uint32_t *c, size_t N, size_t limbs,
                    size_t polys_per_limb, const uint32_t *q, const uint32_t *psi_br,
                    const uint32_t *psi_inv_br, void *workspace, pm_stream_t stream);
+/* The fused product (Alg. 8) on 32-bit words: as pm_polymul_fused. */
+int pm_polymul_fused_u32(const uint32_t *a, const uint32_t *b, uint32_t *c, size_t N, size_t limbs,
+                         size_t polys_per_limb, const uint32_t *q, const uint32_t *psi_br,
+                         const uint32_t *psi_inv_br, void *workspace, pm_stream_t stream);
 /* Workspace bytes pm_polymul_u32 needs for this shape (0 if none). */
 size_t pm_polymul_u32_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
 int pm_make_tables_u32(uint32_t q, size_t N, uint32_t psi, uint32_t *psi_br, uint32_t *psi_inv_br);

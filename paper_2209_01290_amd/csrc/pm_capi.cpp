@@ -252,11 +252,9 @@ size_t polymul_workspace(size_t N, size_t limbs, size_t polys) {
 }
 
 // Eq. 2 over a batch (fused: Alg. 8's rows instead of the pointwise rows).
-// 32-bit words have neither the squaring nor the fused row kernels.
 template <typename W>
 int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t polys, const W* q,
                    const W* psi_br, const W* psi_inv_br, void* workspace, pm_stream_t stream, bool fused) {
-  constexpr bool W64 = sizeof(W) == 8;
   BatchT<W> b;
   int rc;
   if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
@@ -265,11 +263,11 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
     return rc;
   const PassPlan p = plan_for(OP_POLYMUL, b.log2n, N * limbs * polys);
   // the fused product needs N >= 4 (Alg. 8's squared-twiddle identity)
-  fused = W64 && fused && b.log2n >= 2;
+  fused = fused && b.log2n >= 2;
   const bool same = (a == b_);          // one operand: one column pass, no workspace
   // and, unfused, one row transform (the small-batch geometry has no squaring
   // mode: it runs the product with b = a)
-  const bool square = W64 && same && !fused && p.ebx == 4;
+  const bool square = same && !fused && p.ebx == 4;
   // the fused rows exist in the 16-word geometry only
   const int ebx = fused ? 4 : (int)p.ebx;
   const int mode = fused ? ROW_FMUL : (square ? ROW_SQR : ROW_MUL);
@@ -423,6 +421,12 @@ int pm_polymul_u32(const uint32_t* a, const uint32_t* b, uint32_t* c, size_t N, 
                    size_t polys_per_limb, const uint32_t* q, const uint32_t* psi_br, const uint32_t* psi_inv_br,
                    void* workspace, pm_stream_t stream) {
   return polymul_common(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace, stream, false);
+}
+
+int pm_polymul_fused_u32(const uint32_t* a, const uint32_t* b, uint32_t* c, size_t N, size_t limbs,
+                         size_t polys_per_limb, const uint32_t* q, const uint32_t* psi_br,
+                         const uint32_t* psi_inv_br, void* workspace, pm_stream_t stream) {
+  return polymul_common(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace, stream, true);
 }
 
 // ------------------------------------------------------ interleaved layout --

@@ -94,6 +94,7 @@ def load():
             "pm_ntt_fwd_u32": (i32, [vp, sz, sz, sz, u32p, vp, vp]),
             "pm_ntt_inv_u32": (i32, [vp, sz, sz, sz, u32p, vp, vp]),
             "pm_polymul_u32": (i32, [vp, vp, vp, sz, sz, sz, u32p, vp, vp, vp, vp]),
+            "pm_polymul_fused_u32": (i32, [vp, vp, vp, sz, sz, sz, u32p, vp, vp, vp, vp]),
             "pm_polymul_u32_workspace_bytes": (sz, [sz, sz, sz]),
             "pm_make_tables_u32": (i32, [ctypes.c_uint32, sz, ctypes.c_uint32, u32p, u32p]),
         }
@@ -113,7 +114,8 @@ def exported_symbols():
             "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read",
             "pm_polymul_jobs_workspace_bytes", "pm_polymul_jobs", "pm_plan_create", "pm_plan_launch",
             "pm_plan_destroy", "pm_plan_device_bytes", "pm_reduce_apply", "pm_reduce_chain",
-            "pm_ntt_fwd_u32", "pm_ntt_inv_u32", "pm_polymul_u32", "pm_polymul_u32_workspace_bytes",
+            "pm_ntt_fwd_u32", "pm_ntt_inv_u32", "pm_polymul_u32", "pm_polymul_fused_u32",
+            "pm_polymul_u32_workspace_bytes",
             "pm_make_tables_u32", "pm_ntt_fwd_il", "pm_ntt_inv_il", "pm_polymul_il",
             "pm_polymul_il_workspace_bytes", "pm_tune_set_small", "pm_tune_get_small",
             "pm_tune_set_small_batch", "pm_tune_get_small_batch"]
@@ -445,6 +447,13 @@ def pm_make_tables(q, N, psi=None):
     _check(load().pm_make_tables(q, N, psi, fwd.ctypes.data_as(p), inv.ctypes.data_as(p)),
            "pm_make_tables")
     return fwd, inv
+
+
+def pm_polymul_fused_u32(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace=None, stream=None):
+    _check(load().pm_polymul_fused_u32(_dptr32(a, "a"), _dptr32(b, "b"), _dptr32(c, "c"), N, limbs, polys_per_limb,
+                                       _qarr32(q, limbs), _dptr32(psi_br, "psi_br"),
+                                       _dptr32(psi_inv_br, "psi_inv_br"), _wptr(workspace), _stream(stream, a)),
+           "pm_polymul_fused_u32")
 
 
 def pm_make_tables_u32(q, N, psi=None):

@@ -84,9 +84,10 @@ def test_ntt_u32(L, log2n, bits):
     _eq(L.to_host32(y).reshape(a.shape), oracle_ntt_inv(a, qs, iv_o), "ntt_inv_u32 N=%d" % N)
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["eq2", "fused"])
 @pytest.mark.parametrize("bits", list(BITS), ids=list(BITS))
 @pytest.mark.parametrize("log2n", ALL_LOG2N)
-def test_polymul_u32(L, log2n, bits):
+def test_polymul_u32(L, log2n, bits, fused):
     import torch
     N = 1 << log2n
     qs = _moduli(L, N, BITS[bits])
@@ -96,10 +97,11 @@ def test_polymul_u32(L, log2n, bits):
     a, b = operands(N, qs, polys, request=600 + log2n)
     da, db = L.to_device32(a), L.to_device32(b)
     dc = torch.empty_like(da)
-    L.pm_polymul_u32(da, db, dc, N, limbs, polys, qs, dfw, div, _ws(L, N, limbs, polys))
+    fn = L.pm_polymul_fused_u32 if fused else L.pm_polymul_u32
+    fn(da, db, dc, N, limbs, polys, qs, dfw, div, _ws(L, N, limbs, polys))
     _sync()
     got = L.to_host32(dc).reshape(a.shape)
-    _eq(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "polymul_u32 N=%d" % N)
+    _eq(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "polymul%s_u32 N=%d" % ("_fused" if fused else "", N))
     if N <= 512:
         o = oracle.default()
         assert np.array_equal(got[0, 0].astype(np.uint64), o.polymul_schoolbook(a[0, 0], b[0, 0], qs[0]))
@@ -125,10 +127,13 @@ def test_every_pass_plan_u32(L, log2n):
                 L.pm_tune_set(op, log2n, logc)
             dc = torch.empty_like(da)
             L.pm_polymul_u32(da, db, dc, N, limbs, polys, qs, dfw, div, _ws(L, N, limbs, polys))
+            df = torch.empty_like(da)
+            L.pm_polymul_fused_u32(da, db, df, N, limbs, polys, qs, dfw, div, _ws(L, N, limbs, polys))
             x = da.clone()
             L.pm_ntt_fwd_u32(x, N, limbs, polys, qs, dfw)
             _sync()
             _eq(L.to_host32(dc).reshape(a.shape), want, "polymul_u32 N=%d logc=%d" % (N, logc))
+            _eq(L.to_host32(df).reshape(a.shape), want, "fused_u32 N=%d logc=%d" % (N, logc))
             _eq(L.to_host32(x).reshape(a.shape), want_fwd, "ntt_fwd_u32 N=%d logc=%d" % (N, logc))
             L.pm_ntt_inv_u32(x, N, limbs, polys, qs, div)
             _sync()
@@ -138,9 +143,10 @@ def test_every_pass_plan_u32(L, log2n):
             L.pm_tune_set(op, log2n, 0)
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["eq2", "fused"])
 @pytest.mark.parametrize("log2n", [10, 16])
 @pytest.mark.parametrize("alias", ["c=a", "c=b", "a=b", "a=b=c"])
-def test_aliasing_u32(L, log2n, alias):
+def test_aliasing_u32(L, log2n, alias, fused):
     N = 1 << log2n
     qs = _moduli(L, N, [30, 28])
     limbs, polys = 2, 2
@@ -159,7 +165,8 @@ def test_aliasing_u32(L, log2n, alias):
         dc = L.to_device32(np.zeros_like(a))
     else:
         db = dc = da
-    L.pm_polymul_u32(da, db, dc, N, limbs, polys, qs, dfw, div, _ws(L, N, limbs, polys))
+    fn = L.pm_polymul_fused_u32 if fused else L.pm_polymul_u32
+    fn(da, db, dc, N, limbs, polys, qs, dfw, div, _ws(L, N, limbs, polys))
     _sync()
     _eq(L.to_host32(dc).reshape(a.shape), oracle_polymul(a, b, qs, N, fw_o, iv_o), "u32 %s N=%d" % (alias, N))
 
