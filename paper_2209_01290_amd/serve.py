@@ -235,6 +235,25 @@ class GpuExecutor:
                 synth.uniform_mod_device([synth.key(seed, p, l, 0, 1) for l in range(max_limbs)], N,
                                          prm.q[:max_limbs], b[p])
             self.inputs[log2n] = (a, b)
+        # job records per (N, pool entry) for all max_limbs limbs, output
+        # pointers aside: a request takes the first L rows and sets its outputs
+        self.rows, self.c_off = {}, {}
+        for log2n in log2ns:
+            N = 1 << log2n
+            prm = self.tables.get(log2n, max_limbs)
+            a, b = self.inputs[log2n]
+            lidx = np.arange(max_limbs, dtype=np.uint64) * np.uint64(N * 8)
+            self.c_off[log2n] = lidx
+            for p in range(pool):
+                rows = np.zeros(max_limbs, dtype=JOB_DTYPE)
+                rows["log2n"] = log2n
+                rows["count"] = 1
+                rows["q"] = np.array(prm.q[:max_limbs], dtype=np.uint64)
+                rows["psi_br"] = np.uint64(prm.psi_br.data_ptr()) + lidx
+                rows["psi_inv_br"] = np.uint64(prm.psi_inv_br.data_ptr()) + lidx
+                rows["a"] = np.uint64(a[p].data_ptr()) + lidx
+                rows["b"] = np.uint64(b[p].data_ptr()) + lidx
+                self.rows[(log2n, p)] = rows
         torch.cuda.synchronize()
 
     def budget(self):
@@ -250,23 +269,9 @@ class GpuExecutor:
 
     def job_rows(self, r, out_ptr=None):
         """pm_job records of request r (output in its arena slot, or at out_ptr)."""
-        N = 1 << r.log2n
-        prm = self.tables.get(r.log2n, 0)
-        a, b = self.inputs[r.log2n]
-        p = r.rid % self.pool
-        L = r.limbs
-        rows = np.zeros(L, dtype=JOB_DTYPE)
-        rows["log2n"] = r.log2n
-        rows["count"] = 1
-        rows["q"] = np.array(prm.q[:L], dtype=np.uint64)
-        lidx = np.arange(L, dtype=np.uint64)
-        step = np.uint64(N * 8)
-        rows["psi_br"] = np.uint64(prm.psi_br.data_ptr()) + lidx * step
-        rows["psi_inv_br"] = np.uint64(prm.psi_inv_br.data_ptr()) + lidx * step
-        rows["a"] = np.uint64(a[p].data_ptr()) + lidx * step
-        rows["b"] = np.uint64(b[p].data_ptr()) + lidx * step
+        rows = self.rows[(r.log2n, r.rid % self.pool)][:r.limbs].copy()
         base = out_ptr if out_ptr is not None else self.base + r.alloc[0]
-        rows["c"] = np.uint64(base) + lidx * step
+        rows["c"] = np.uint64(base) + self.c_off[r.log2n][:r.limbs]
         return rows
 
     def inputs_of(self, r):
