@@ -28,6 +28,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import gc
 import json
 import time
 
@@ -117,7 +118,18 @@ class Engine:
         self.batch_ws = batch_ws_bytes if batch_ws_bytes is not None else executor.batch_workspace_bytes()
 
     def run(self, trace, time_scale: float = 1.0, on_complete=None):
-        """trace: [(arrival_s, log2n, limbs)] sorted by arrival. Returns stats."""
+        """trace: [(arrival_s, log2n, limbs)] sorted by arrival. Returns stats.
+        The garbage collector is held off while the loop runs (its pauses
+        would show up as request latency)."""
+        gc_was = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(trace, time_scale, on_complete)
+        finally:
+            if gc_was:
+                gc.enable()
+
+    def _run(self, trace, time_scale, on_complete):
         reqs = [Request(i, t * time_scale, n, L) for i, (t, n, L) in enumerate(trace)]
         queue = collections.deque()
         inflight = collections.deque()          # (handle, [requests], unused)
@@ -312,8 +324,17 @@ class GpuExecutor:
         pass
 
 
+def warm_up(ex):
+    """One request per size through the batched entry point before any timing:
+    the first launch of each kernel loads its code, which would otherwise land
+    in the first requests' latency."""
+    for i, log2n in enumerate(workloads.SERVE_LOG2N):
+        ex.run_alone(Request(i, 0.0, log2n, 2))
+
+
 def run_rates(rates, nreq, budget_gib=32.0, streams=3, seed=SEED, verbose=True, ex=None):
     ex = ex or GpuExecutor(int(budget_gib * (1 << 30)), streams=streams, seed=seed)
+    warm_up(ex)
     out = []
     for rate in rates:
         trace = [(t, n, L) for (t, n, L) in workloads.serving_requests(seed + int(rate), nreq, rate)]
