@@ -26,7 +26,15 @@
  *     a primitive 2N-th root of unity psi (psi^N = q-1); entry 0 is never read.
  *     pm_make_tables() builds them.
  *   - Inputs must be canonical (< q); non-canonical input gives unspecified
- *     (but memory-safe) output.
+ *     (but memory-safe) output. With the environment variable PM_VALIDATE
+ *     set (to anything but "0"), every entry point that takes coefficients or
+ *     twiddle tables also checks, on the device, that each input word is below
+ *     its limb's modulus and that each table's entry N/2 (psi, or psi^-1 for
+ *     an inverse table) satisfies psi^N = q - 1, and returns PM_EINVAL
+ *     otherwise, before any output is written. These checks allocate a little
+ *     device memory and synchronise the stream (a debugging aid; not for use
+ *     under graph capture). pm_plan_create checks the tables, pm_plan_launch
+ *     the inputs.
  *   - Calls are stream-ordered and asynchronous: `stream` is a hipStream_t
  *     (NULL = the default stream). Argument errors are reported before any
  *     work is enqueued.

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <initializer_list>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -34,6 +36,15 @@ int hip_fail(hipError_t e, const char* what) {
 typedef unsigned __int128 u128;
 
 bool is_pow2(size_t n) { return n && !(n & (n - 1)); }
+
+uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+uint64_t powmod_h(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  for (b %= m; e; e >>= 1, b = mulmod_h(b, b, m))
+    if (e & 1) r = mulmod_h(r, b, m);
+  return r;
+}
 unsigned log2u(size_t n) { unsigned l = 0; while (((size_t)1 << l) < n) ++l; return l; }
 
 }  // namespace
@@ -93,6 +104,60 @@ bool make_mod32(uint32_t q, Mod32* M) {
 
 // KIND_WIDE on 32-bit words: every modulus has m <= 29 (no final shift).
 int mod_kind32(const Mod32& M) { return M.t ? KIND_ANY : KIND_WIDE; }
+
+// ------------------------------------------------------------ PM_VALIDATE --
+// With PM_VALIDATE set (and not "0"), calls also check what the kernels take
+// as preconditions: every input word is canonical (< q of its limb) and each
+// twiddle table's psi = table[N/2] satisfies psi^N = q - 1 (for an inverse
+// table, psi^-1 does too). The checks read device memory, allocate a little
+// and synchronise the stream: a debugging aid, not for graph capture.
+bool validate_enabled() {
+  const char* v = std::getenv("PM_VALIDATE");
+  return v && *v && std::strcmp(v, "0") != 0;
+}
+
+int validate_canonical(const void* x, int word_bytes, size_t per_limb, size_t limbs, const uint64_t* q,
+                       const std::string& name, hipStream_t s) {
+  if (per_limb == 0 || limbs == 0) return PM_OK;
+  uint64_t* qd = nullptr;
+  uint32_t* fd = nullptr;
+  std::vector<uint32_t> flags(limbs, 0);
+  hipError_t e = hipMalloc((void**)&qd, limbs * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&fd, limbs * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemcpyAsync(qd, q, limbs * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(fd, 0, limbs * sizeof(uint32_t), s);
+  for (size_t l0 = 0; e == hipSuccess && l0 < limbs; l0 += 65535) {
+    const size_t nl = std::min((size_t)65535, limbs - l0);
+    e = launch_canon((const char*)x + l0 * per_limb * word_bytes, word_bytes, per_limb, (uint32_t)nl, qd + l0,
+                     fd + l0, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), fd, limbs * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (qd) (void)hipFree(qd);
+  if (fd) (void)hipFree(fd);
+  if (e != hipSuccess) return hip_fail(e, "input validation");
+  for (size_t l = 0; l < limbs; ++l)
+    if (flags[l])
+      return fail(PM_EINVAL, name + ": limb " + std::to_string(l) + " holds a word >= q (inputs must be canonical)");
+  return PM_OK;
+}
+
+int validate_psi(const void* tw, int word_bytes, size_t N, size_t limbs, const uint64_t* q, const std::string& name,
+                 hipStream_t s) {
+  std::vector<uint64_t> psi(limbs, 0);
+  std::vector<uint32_t> psi32(word_bytes == 4 ? limbs : 0, 0);
+  void* dst = word_bytes == 4 ? (void*)psi32.data() : (void*)psi.data();
+  hipError_t e = hipMemcpy2DAsync(dst, word_bytes, (const char*)tw + (N / 2) * word_bytes, N * word_bytes,
+                                  word_bytes, limbs, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "table validation");
+  for (size_t l = 0; l < limbs; ++l) {
+    const uint64_t p = word_bytes == 4 ? psi32[l] : psi[l];
+    if (p >= q[l] || powmod_h(p, N, q[l]) != q[l] - 1)
+      return fail(PM_EINVAL, name + ": limb " + std::to_string(l) + ": entry N/2 (psi) fails psi^N = q - 1");
+  }
+  return PM_OK;
+}
 
 }  // namespace pm
 
@@ -216,6 +281,21 @@ int for_chunks(const BatchT<W>& b, F f) {
   return PM_OK;
 }
 
+// PM_VALIDATE checks of a batch: input spans of polys * N words per limb,
+// and twiddle tables.
+template <typename W>
+int validate_batch(const BatchT<W>& b, std::initializer_list<std::pair<const W*, const char*>> inputs,
+                   std::initializer_list<std::pair<const W*, const char*>> tables, hipStream_t s) {
+  std::vector<uint64_t> q(b.limbs);
+  for (size_t l = 0; l < b.limbs; ++l) q[l] = b.mods[l].q;
+  int rc;
+  for (const auto& in : inputs)
+    if ((rc = validate_canonical(in.first, sizeof(W), b.polys * b.N, b.limbs, q.data(), in.second, s))) return rc;
+  for (const auto& t : tables)
+    if ((rc = validate_psi(t.first, sizeof(W), b.N, b.limbs, q.data(), t.second, s))) return rc;
+  return PM_OK;
+}
+
 // The merged transforms (Alg. 5 / Alg. 6 halved) over a batch, in place.
 template <typename W>
 int ntt_common(W* x, size_t N, size_t limbs, size_t polys, const W* q, const W* tw, pm_stream_t stream, bool inv) {
@@ -225,6 +305,9 @@ int ntt_common(W* x, size_t N, size_t limbs, size_t polys, const W* q, const W* 
   if ((rc = check_ptr<W>(x, "x")) || (rc = check_ptr<W>(tw, inv ? "psi_inv_br" : "psi_br"))) return rc;
   const PassPlan p = plan_for(inv ? OP_NTT_INV : OP_NTT_FWD, b.log2n, N * limbs * polys);
   hipStream_t s = (hipStream_t)stream;
+  if (validate_enabled() &&
+      (rc = validate_batch<W>(b, {{x, "x"}}, {{tw, inv ? "psi_inv_br" : "psi_br"}}, s)))
+    return rc;
   rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSetT<W>& ls) -> hipError_t {
     W* xs = x + l0 * polys * N;
     const W* t = tw + l0 * N;
@@ -278,6 +361,9 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
   if (p.R > 1 && !same && (rc = check_ptr<W>(workspace, "workspace"))) return rc;
   W* ws = (W*)workspace;
   hipStream_t s = (hipStream_t)stream;
+  if (validate_enabled() &&
+      (rc = validate_batch<W>(b, {{a, "a"}, {b_, "b"}}, {{psi_br, "psi_br"}, {psi_inv_br, "psi_inv_br"}}, s)))
+    return rc;
   rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSetT<W>& ls) -> hipError_t {
     const size_t base = l0 * polys * N;
     const W* tf = psi_br + l0 * N;
@@ -318,6 +404,9 @@ int pm_barrett_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t 
   if ((rc = check_ptr(a, "a")) || (rc = check_ptr(b, "b")) || (rc = check_ptr(c, "c"))) return rc;
   Mod M;
   if (!make_mod(q, &M)) return fail(PM_EINVAL, "q must satisfy 2 <= q < 2^62");
+  if (validate_enabled() && ((rc = validate_canonical(a, 8, n, 1, &q, "a", (hipStream_t)stream)) ||
+                             (rc = validate_canonical(b, 8, n, 1, &q, "b", (hipStream_t)stream))))
+    return rc;
   hipError_t e;
   {
     ProfScope ps((hipStream_t)stream, "mulmod");
@@ -375,6 +464,9 @@ int pm_polymul_stagewise(const uint64_t* a, const uint64_t* b_, uint64_t* c, siz
   if (!square && (rc = check_ptr(workspace, "workspace"))) return rc;
   uint64_t* ws = (uint64_t*)workspace;
   hipStream_t s = (hipStream_t)stream;
+  if (validate_enabled() &&
+      (rc = validate_batch<uint64_t>(b, {{a, "a"}, {b_, "b"}}, {{psi_br, "psi_br"}, {psi_inv_br, "psi_inv_br"}}, s)))
+    return rc;
   rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
     const size_t base = l0 * polys * N;
     const uint64_t* tf = psi_br + l0 * N;
@@ -471,6 +563,9 @@ static int ntt_common_il(uint64_t* x, size_t N, size_t limbs, size_t polys, cons
   int sz[32];
   const int np = il_plan(b.log2n, IL_MAXR, sz);
   hipStream_t s = (hipStream_t)stream;
+  if (validate_enabled() &&
+      (rc = validate_batch<uint64_t>(b, {{x, "x"}}, {{tw, inv ? "psi_inv_br" : "psi_br"}}, s)))
+    return rc;
   rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
     uint64_t* xs = x + l0 * polys * N;
     const uint64_t* t = tw + l0 * N;
@@ -529,6 +624,9 @@ int pm_polymul_il(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, 
   if (np > 1 && !same && (rc = check_ptr(workspace, "workspace"))) return rc;
   uint64_t* ws = (uint64_t*)workspace;
   hipStream_t s = (hipStream_t)stream;
+  if (validate_enabled() &&
+      (rc = validate_batch<uint64_t>(b, {{a, "a"}, {b_, "b"}}, {{psi_br, "psi_br"}, {psi_inv_br, "psi_inv_br"}}, s)))
+    return rc;
   rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSet& ls) -> hipError_t {
     const size_t base = l0 * polys * N;
     const uint64_t* tf = psi_br + l0 * N;
@@ -563,14 +661,6 @@ int pm_polymul_il(const uint64_t* a, const uint64_t* b_, uint64_t* c, size_t N, 
 
 // ------------------------------------------------------------ host helpers --
 
-static uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
-
-static uint64_t powmod_h(uint64_t b, uint64_t e, uint64_t m) {
-  uint64_t r = 1 % m;
-  for (b %= m; e; e >>= 1, b = mulmod_h(b, b, m))
-    if (e & 1) r = mulmod_h(r, b, m);
-  return r;
-}
 
 // Miller-Rabin with the seven Jaeschke/Sinclair bases, exact for 64-bit n.
 static bool probable_prime(uint64_t n) {

@@ -82,6 +82,11 @@ struct IlArgs {
   const LimbSet* ls;
 };
 hipError_t launch_il(int logr, int kind, int mode, const IlArgs& a, hipStream_t s);
+
+// PM_VALIDATE scan (pm_validate.hip): flags_dev[l] = 1 if some word of limb
+// l's span of x (per_limb words of word_bytes each) is >= qs_dev[l].
+hipError_t launch_canon(const void* x, int word_bytes, size_t per_limb, uint32_t limbs, const uint64_t* qs_dev,
+                        uint32_t* flags_dev, hipStream_t s);
 hipError_t launch_stage(int kind, bool inv, const ColArgs& a, uint32_t log2m, hipStream_t s);
 hipError_t launch_pointwise(int kind, const uint64_t* A, const uint64_t* B, uint64_t* C, uint32_t log2n,
                             uint32_t polys, uint32_t limbs, const LimbSet& ls, hipStream_t s);

@@ -174,6 +174,24 @@ struct pm_plan {
   bool use_graph = true;
 };
 
+// PM_VALIDATE checks of a job list: inputs canonical, and (tables) each
+// job's twiddle tables hold a psi with psi^N = q - 1.
+static int validate_jobs(const Layout& L, bool tables, hipStream_t s) {
+  for (size_t j = 0; j < L.jobs.size(); ++j) {
+    const JobDev& J = L.jobs[j];
+    const uint64_t q = J.mod.q;
+    const size_t N = (size_t)1 << J.log2n, words = (size_t)J.count * N;
+    const std::string tag = "job " + std::to_string(j) + ": ";
+    int rc;
+    if ((rc = validate_canonical(J.a, 8, words, 1, &q, tag + "a", s))) return rc;
+    if (J.b != J.a && (rc = validate_canonical(J.b, 8, words, 1, &q, tag + "b", s))) return rc;
+    if (tables && ((rc = validate_psi(J.tf, 8, N, 1, &q, tag + "psi_br", s)) ||
+                   (rc = validate_psi(J.ti, 8, N, 1, &q, tag + "psi_inv_br", s))))
+      return rc;
+  }
+  return PM_OK;
+}
+
 extern "C" {
 
 size_t pm_polymul_jobs_workspace_bytes(const pm_job* jobs, size_t njobs) {
@@ -192,6 +210,7 @@ int pm_polymul_jobs(const pm_job* jobs, size_t njobs, void* workspace, size_t wo
   if (workspace_bytes < need)
     return set_error(PM_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
   hipStream_t s = (hipStream_t)stream;
+  if (validate_enabled() && (rc = validate_jobs(L, true, s))) return rc;
   char* base = (char*)workspace;
   {
     std::lock_guard<std::mutex> lk(g_stage_mu);
@@ -225,6 +244,7 @@ int pm_plan_create(pm_plan** out, const pm_job* jobs, size_t njobs, unsigned fla
   if (!p) return set_error(PM_ENOMEM, "host allocation failed");
   int rc = build_layout(jobs, njobs, &p->L);
   if (rc) { delete p; return rc; }
+  if (validate_enabled() && (rc = validate_jobs(p->L, true, nullptr))) { delete p; return rc; }
   p->use_graph = !(flags & PM_PLAN_NO_GRAPH);
   (void)hipGetDevice(&p->device);
   p->dev_bytes = p->L.ws_off + p->L.ws_bytes;
@@ -262,6 +282,10 @@ int pm_plan_launch(pm_plan* p, pm_stream_t stream) {
   (void)hipGetDevice(&dev);
   if (dev != p->device) return set_error(PM_EINVAL, "plan belongs to another device");
   hipStream_t s = (hipStream_t)stream;
+  if (validate_enabled()) {
+    const int rc = validate_jobs(p->L, false, s);
+    if (rc) return rc;
+  }
   hipError_t e;
   if (p->use_graph) {
     ProfScope ps(s, "plan_graph");

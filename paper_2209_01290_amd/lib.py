@@ -385,13 +385,14 @@ def pm_tune_get_small_batch():
 
 
 def apply_tune_db(path=None):
-    """Install the pass plans of an autotuner database (see tune.py): the
+    """Install the pass plans of an autotuner database (see tune.py; default:
+    $PM_TUNE_DB, else the packaged MI355X database): the
     throughput plans ("choices") and, if present, the small-batch plans
     ("small": {"max_words": W, "choices": {op: {log2n: [logc, words_per_thread]}}});
     returns the number of entries applied, 0 if the file does not exist."""
     import json
     if path is None:
-        path = os.path.join(PKG, "tune_db", "gfx950.json")
+        path = os.environ.get("PM_TUNE_DB") or os.path.join(PKG, "tune_db", "gfx950.json")
     if not os.path.exists(path):
         return 0
     with open(path) as f:
