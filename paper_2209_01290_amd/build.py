@@ -1,9 +1,13 @@
 """Build ``libpm.so`` (HIP kernels for gfx950 plus the C-ABI host runtime).
 
 Every ``csrc/*.hip`` and ``csrc/*.cpp`` file is compiled by hipcc in parallel
-into ``_build/`` and linked into ``paper_2209_01290_amd/libpm.so``. Usage:
+into ``_build/`` and linked into ``paper_2209_01290_amd/libpm.so``. The
+``poison`` variant (``libpm_poison.so``, objects in ``_build_poison/``) is the
+same library with PM_POISON_LDS=1: every LDS exchange first fills the row's
+LDS with words above every modulus, a debugging build that turns a missing
+barrier or an unwritten slot into a wrong result. Usage:
 
-    python -m paper_2209_01290_amd.build [--force] [-j N]
+    python -m paper_2209_01290_amd.build [--force] [-j N] [--variant poison]
 """
 from __future__ import annotations
 
@@ -44,8 +48,11 @@ def _filter(out: str) -> str:
     return "\n".join(l for l in out.splitlines() if "packed-fp32-ops" not in l)
 
 
-def _compile(src: str, obj: str) -> None:
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+VARIANTS = {"": ([], "_build", "libpm.so"), "poison": (["-DPM_POISON_LDS=1"], "_build_poison", "libpm_poison.so")}
+
+
+def _compile(src: str, obj: str, extra=()) -> None:
+    cmd = [HIPCC] + CFLAGS + list(extra) + ["-c", src, "-o", obj]
     p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     msg = _filter(p.stdout)
     if p.returncode != 0:
@@ -54,7 +61,10 @@ def _compile(src: str, obj: str) -> None:
         sys.stderr.write(msg + "\n")
 
 
-def build(force: bool = False, jobs: int | None = None, verbose: bool = True) -> str:
+def build(force: bool = False, jobs: int | None = None, verbose: bool = True, variant: str = "") -> str:
+    extra, bdir, lname = VARIANTS[variant]
+    BUILD = os.path.join(PKG, bdir)
+    LIB = os.path.join(PKG, lname)
     os.makedirs(BUILD, exist_ok=True)
     deps_mtime = max(os.path.getmtime(d) for d in _deps())
     todo = []
@@ -70,7 +80,7 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = True) ->
         if verbose:
             print("[build] compiling %d file(s) with %d job(s)" % (len(todo), jobs), flush=True)
         with cf.ThreadPoolExecutor(jobs) as ex:
-            futs = [ex.submit(_compile, s, o) for s, o in todo]
+            futs = [ex.submit(_compile, s, o, extra) for s, o in todo]
             for f in futs:
                 f.result()
     if todo or force or not os.path.exists(LIB):
@@ -89,8 +99,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--force", action="store_true")
     ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("--variant", default="", choices=sorted(VARIANTS))
     a = ap.parse_args()
-    build(force=a.force, jobs=a.j)
+    build(force=a.force, jobs=a.j, variant=a.variant)
 
 
 if __name__ == "__main__":

@@ -203,6 +203,13 @@ __device__ __forceinline__ void gmem_put(W* __restrict__ row, const W (&x)[RowGe
 template <int GEO, int FROM, int TO, typename W>
 __device__ __forceinline__ void exchange(W* lds, W (&x)[RowGeom<GEO>::E], uint32_t t) {
   __syncthreads();
+#if PM_POISON_LDS
+  // Debug build: fill the row's LDS with words above every modulus before
+  // each exchange, so a slot read without being written in this exchange (a
+  // missing barrier or an indexing error) corrupts the result.
+  for (uint32_t i = t; i < (uint32_t)RowGeom<GEO>::LDS_ROW; i += RowGeom<GEO>::T) lds[i] = ~(W)0;
+  __syncthreads();
+#endif
   lds_put<GEO, FROM>(lds, x, t);
   __syncthreads();
   lds_get<GEO, TO>(lds, x, t);
