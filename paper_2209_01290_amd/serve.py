@@ -109,32 +109,43 @@ BATCH_WS_SLACK = 8192
 
 
 class Engine:
+    """deadline_s: a request still waiting in the queue that long after its
+    arrival is dropped (state "timeout"); admitted requests always complete.
+    run(cancels=...) takes {request id: time}: a request still queued at that
+    time is dropped (state "cancelled"); a request already admitted or on the
+    device completes and is counted as a late cancellation."""
+
     def __init__(self, executor, budget_bytes: int, streams: int = 3, max_batch_products: int = 4096,
-                 batch_ws_bytes: int | None = None):
+                 batch_ws_bytes: int | None = None, deadline_s: float | None = None):
         self.ex = executor
         self.arena = Arena(budget_bytes)
         self.streams = streams
         self.max_batch_products = max_batch_products
         self.batch_ws = batch_ws_bytes if batch_ws_bytes is not None else executor.batch_workspace_bytes()
+        self.deadline_s = deadline_s
 
-    def run(self, trace, time_scale: float = 1.0, on_complete=None):
+    def run(self, trace, time_scale: float = 1.0, on_complete=None, cancels=None):
         """trace: [(arrival_s, log2n, limbs)] sorted by arrival. Returns stats.
         The garbage collector is held off while the loop runs (its pauses
         would show up as request latency)."""
         gc_was = gc.isenabled()
         gc.disable()
         try:
-            return self._run(trace, time_scale, on_complete)
+            return self._run(trace, time_scale, on_complete, cancels or {})
         finally:
             if gc_was:
                 gc.enable()
 
-    def _run(self, trace, time_scale, on_complete):
+    def _run(self, trace, time_scale, on_complete, cancels):
         reqs = [Request(i, t * time_scale, n, L) for i, (t, n, L) in enumerate(trace)]
         queue = collections.deque()
         inflight = collections.deque()          # (handle, [requests], unused)
         max_inflight = 0
-        rejected = []
+        rejected = []                           # rejected at arrival, timed out or cancelled
+        late_cancel = 0
+        cancel_at = sorted((t * time_scale, rid) for rid, t in cancels.items())
+        drop_now, drop_on_arrival = set(), set()
+        ci = 0
         nxt = 0
         done = 0
         batches, batch_sizes, max_queue = 0, [], 0
@@ -143,13 +154,42 @@ class Engine:
             now = time.monotonic() - t0
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
                 r = reqs[nxt]
-                if footprint(r.log2n, r.limbs) > self.arena.size or \
+                if r.rid in drop_on_arrival:
+                    drop_on_arrival.discard(r.rid)
+                    r.state = "cancelled"
+                    r.t_done = now
+                    rejected.append(r)
+                elif footprint(r.log2n, r.limbs) > self.arena.size or \
                         batch_workspace(r.log2n, r.limbs) > self.batch_ws - BATCH_WS_SLACK:
                     r.state = "rejected"
                     rejected.append(r)
                 else:
                     queue.append(r)
                 nxt += 1
+            # cancellations due by now: queued requests leave the queue, ones
+            # not yet arrived are dropped on arrival, admitted ones complete
+            while ci < len(cancel_at) and cancel_at[ci][0] <= now:
+                r = reqs[cancel_at[ci][1]]
+                if r.state == "pending":
+                    (drop_now if r.rid < nxt else drop_on_arrival).add(r.rid)
+                elif r.state == "admitted":
+                    late_cancel += 1
+                ci += 1
+            expired = self.deadline_s is not None and queue and now - queue[0].arrival > self.deadline_s
+            if expired or drop_now:
+                kept = collections.deque()
+                for r in queue:
+                    if r.rid in drop_now:
+                        r.state = "cancelled"
+                    elif self.deadline_s is not None and now - r.arrival > self.deadline_s:
+                        r.state = "timeout"
+                    else:
+                        kept.append(r)
+                        continue
+                    r.t_done = now
+                    rejected.append(r)
+                queue = kept
+                drop_now.clear()
             max_queue = max(max_queue, len(queue))
             # completions
             while inflight and self.ex.done(inflight[0][0]):
@@ -198,7 +238,11 @@ class Engine:
         n16 = sum(((1 << r.log2n) * r.log2n * r.limbs) for r in ok) / float((1 << 16) * 16)
         span = (max(r.t_done for r in ok) - min(r.arrival for r in ok)) if ok else 0.0
         return {
-            "requests": len(reqs), "completed": len(ok), "rejected": len(rejected),
+            "requests": len(reqs), "completed": len(ok),
+            "rejected": sum(1 for r in rejected if r.state == "rejected"),
+            "timed_out": sum(1 for r in rejected if r.state == "timeout"),
+            "cancelled": sum(1 for r in rejected if r.state == "cancelled"),
+            "late_cancellations": late_cancel,
             "limb_products": int(sum(r.limbs for r in ok)),
             "wall_s": round(wall, 4),
             "throughput_req_s": round(len(ok) / span, 1) if span > 0 else None,

@@ -95,3 +95,39 @@ def test_arena_allocator():
     a.release(*z)
     assert a.used == 0 and a.free == [(0, 1 << 20)]   # fully coalesced
     assert a.alloc(2 << 20) is None
+
+
+def test_queue_deadline_times_out_and_frees_nothing_admitted():
+    """With a tiny arena the queue backs up; requests waiting longer than the
+    deadline leave as timeouts, every other request completes, and the arena
+    ends empty."""
+    ex = FakeExecutor(us_per_product=400.0)
+    tr = _trace(120, 50000.0, seed=3)
+    one = max(serve.footprint(n, L) for _, n, L in tr)
+    eng = serve.Engine(ex, budget_bytes=one, streams=2, deadline_s=0.002)
+    st = eng.run(tr)
+    reqs = st["_requests"]
+    assert st["timed_out"] > 0 and st["completed"] + st["timed_out"] == 120
+    assert all(r.state in ("done", "timeout") for r in reqs)
+    for r in reqs:
+        if r.state == "timeout":
+            assert r.t_admit is None and r.t_done - r.arrival > 0.002 - 1e-9
+    assert eng.arena.used == 0
+
+
+def test_cancellation():
+    """Cancelled while queued or before arrival: dropped; cancelled after
+    admission: completes and counts as a late cancellation."""
+    ex = FakeExecutor(us_per_product=300.0)
+    tr = _trace(100, 40000.0, seed=4)
+    one = max(serve.footprint(n, L) for _, n, L in tr)
+    cancels = {5: 0.0, 60: tr[60][0] + 1e-6, 99: 0.0}   # 99 and 5 before they arrive (5 arrives later than 0)
+    eng = serve.Engine(ex, budget_bytes=2 * one, streams=2)
+    st = eng.run(tr, cancels=cancels)
+    reqs = st["_requests"]
+    assert reqs[99].state == "cancelled" and reqs[99].t_admit is None
+    assert reqs[5].state == "cancelled"
+    assert st["cancelled"] + st["completed"] == 100 and st["cancelled"] >= 2
+    assert reqs[60].state in ("cancelled", "done")
+    assert st["cancelled"] + st["late_cancellations"] <= len(cancels)
+    assert eng.arena.used == 0
