@@ -248,13 +248,14 @@ int pm_tune_get(int op, unsigned log2n);   /* current logc, or PM_EINVAL */
 /*
  * Small-batch plans: a batch too small to fill the GPU with 16-word threads
  * (a single transform or product is latency-bound: a row of 2^logc words
- * runs on one CU) can use a plan with 4 words per thread in the row pass
- * (rounds of two stages, four times the threads per row) and shorter rows,
- * spreading one transform over more CUs; this is the role of the paper's
+ * runs on one CU) can use a plan with 4 words per thread (rounds of two
+ * stages, four times the threads) in both passes and shorter rows, spreading
+ * one transform over more CUs; this is the role of the paper's
  * latency-optimised single- and multi-block kernels (Sec. V-A, V-B).
  * pm_tune_set_small installs (logc, words_per_thread) for (op, N):
- * words_per_thread 4 needs 5 <= logc <= 12 (pm_polymul_fused keeps 16),
- * 16 any valid split; logc = 0 removes the plan. A call over
+ * words_per_thread 4 needs 5 <= logc <= 12 and N / 2^logc in 2^0, 2^2..2^7
+ * (or 2 with logc >= 8; pm_polymul_fused keeps 16 words per thread in its
+ * rows), 16 any valid split; logc = 0 removes the plan. A call over
  * N * limbs * polys_per_limb <= pm_tune_get_small_batch() words uses the
  * small-batch plan of its (op, N) if one is installed; the threshold is 0
  * (no small-batch plans used) until pm_tune_set_small_batch sets it. Results

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/pm.h"
+#include "pm_colq.hpp"
 #include "pm_host.hpp"
 #include "pm_internal.hpp"
 #include "pm_plan.hpp"
@@ -232,16 +233,19 @@ const char* row_name(int mode, int logc, int ebx) {
   return names[(ebx == 2 ? 75 : 0) + mode * 15 + logc].c_str();
 }
 
+// "col_fwd_r4" (one thread per column), "colq_fwd_r6" (four words per thread)
 template <typename W>
-const char* col_name(bool inv, int logr) {
+const char* col_name(bool inv, int logr, bool quad) {
   static const std::vector<std::string> names = [] {
-    const std::string tag = sizeof(W) == 4 ? "col32_" : "col_";
+    const std::string w = sizeof(W) == 4 ? "32_" : "_";
     std::vector<std::string> v;
-    for (int i = 0; i < 2; ++i)
-      for (int r = 0; r <= 5; ++r) v.push_back(tag + (i ? "inv_r" : "fwd_r") + std::to_string(r));
+    for (int q = 0; q < 2; ++q)
+      for (int i = 0; i < 2; ++i)
+        for (int r = 0; r <= 7; ++r)
+          v.push_back(std::string(q ? "colq" : "col") + w + (i ? "inv_r" : "fwd_r") + std::to_string(r));
     return v;
   }();
-  return names[(inv ? 6 : 0) + logr].c_str();
+  return names[(quad ? 16 : 0) + (inv ? 8 : 0) + logr].c_str();
 }
 
 template <typename W>
@@ -250,10 +254,13 @@ hipError_t run_row(int logc, int kind, int mode, const RowArgsT<W>& a, hipStream
   return launch_row(logc, kind, mode, a, s, ebx);
 }
 
+// The column pass of a plan: four words per thread (k_colq) for the
+// small-batch geometry, else one thread per column (k_col).
 template <typename W>
-hipError_t run_col(int logr, int kind, bool inv, const ColArgsT<W>& a, hipStream_t s) {
-  ProfScope ps(s, col_name<W>(inv, logr));
-  return launch_col(logr, kind, inv, a, s);
+hipError_t run_col(int logr, int kind, bool inv, const ColArgsT<W>& a, hipStream_t s, int ebx) {
+  const bool quad = ebx == 2 && logr >= (int)PM_COLQ_MIN_LOGR;
+  ProfScope ps(s, col_name<W>(inv, logr, quad));
+  return quad ? launch_colq(logr, kind, inv, a, s) : launch_col(logr, kind, inv, a, s);
 }
 
 hipError_t run_stage(int kind, bool inv, const ColArgs& a, uint32_t log2m, hipStream_t s) {
@@ -316,11 +323,11 @@ int ntt_common(W* x, size_t N, size_t limbs, size_t polys, const W* q, const W* 
     ColArgsT<W> ca{xs, xs, nullptr, nullptr, t, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
     hipError_t e;
     if (!inv) {
-      if (p.R > 1 && (e = run_col(p.logr, b.kind, false, ca, s)) != hipSuccess) return e;
+      if (p.R > 1 && (e = run_col(p.logr, b.kind, false, ca, s, p.ebx)) != hipSuccess) return e;
       return run_row(p.logc, b.kind, ROW_FWD, ra, s, p.ebx);
     }
     if ((e = run_row(p.logc, b.kind, ROW_INV, ra, s, p.ebx)) != hipSuccess) return e;
-    if (p.R > 1) return run_col(p.logr, b.kind, true, ca, s);
+    if (p.R > 1) return run_col(p.logr, b.kind, true, ca, s, p.ebx);
     return hipSuccess;
   });
   if (rc == PM_OK) g_err.clear();
@@ -377,13 +384,13 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
     W* wb = same ? c + base : ws + base;
     ColArgsT<W> cf{A + base, c + base, B + base, wb, tf, b.log2n, (uint32_t)polys, (uint32_t)nl,
                    same ? 1u : 2u, &ls};
-    hipError_t e = run_col(p.logr, b.kind, false, cf, s);
+    hipError_t e = run_col(p.logr, b.kind, false, cf, s, p.ebx);
     if (e != hipSuccess) return e;
     RowArgsT<W> ra{c + base, square ? nullptr : wb, c + base, tf, ti, b.log2n, p.R, (uint32_t)polys,
                    (uint32_t)nl, &ls};
     if ((e = run_row(p.logc, b.kind, mode, ra, s, ebx)) != hipSuccess) return e;
     ColArgsT<W> ci{c + base, c + base, nullptr, nullptr, ti, b.log2n, (uint32_t)polys, (uint32_t)nl, 1, &ls};
-    return run_col(p.logr, b.kind, true, ci, s);
+    return run_col(p.logr, b.kind, true, ci, s, p.ebx);
   });
   if (rc == PM_OK) g_err.clear();
   return rc;

@@ -21,6 +21,16 @@ bool valid_split(unsigned log2n, unsigned logc) {
   return true;
 }
 
+// The small-batch geometry: rows of 2^5..2^12 words; a column pass of
+// 2^2..2^7 rows runs with four words per thread (any number of columns), a
+// column pass of 2 rows with one thread per column (>= 256 columns).
+bool valid_small_split(unsigned log2n, unsigned logc) {
+  if (logc < 5 || logc > 12 || logc > log2n) return false;
+  const unsigned logr = log2n - logc;
+  if (logr == 1) return logc >= 8;
+  return logr <= PM_COLQ_MAX_LOGR;
+}
+
 uint32_t default_logc(int op, unsigned log2n) {
   // Rows of 2^12 words (32 KiB of LDS, 256 threads) keep four workgroups per
   // CU; a whole polynomial up to 2^13 words (fused product) or 2^14 words
@@ -44,8 +54,8 @@ bool plan_small_set(int op, unsigned log2n, unsigned logc, unsigned ebx) {
   if (op < 0 || op >= OP_COUNT || log2n < 1 || log2n > PM_MAX_LOG2N) return false;
   if (logc == 0) { g_small[op][log2n].store(0); return true; }
   if (ebx != 2 && ebx != 4) return false;
-  if (!valid_split(log2n, logc)) return false;
-  if (ebx == 2 && (logc < 5 || logc > 12)) return false;
+  if (ebx == 4 && !valid_split(log2n, logc)) return false;
+  if (ebx == 2 && !valid_small_split(log2n, logc)) return false;
   g_small[op][log2n].store(logc | (ebx << 8));
   return true;
 }

@@ -12,6 +12,9 @@ namespace pm {
 constexpr unsigned PM_MAX_LOG2N = 17;
 constexpr unsigned PM_MAX_LOGC = 14;     // largest row held in one workgroup's LDS
 constexpr unsigned PM_MAX_LOGR = 5;      // largest column radix held in registers
+// column radices of the four-word column pass (small-batch plans)
+constexpr unsigned PM_COLQ_MIN_LOGR = 2;
+constexpr unsigned PM_COLQ_MAX_LOGR = 7;
 
 enum { OP_NTT_FWD = 0, OP_NTT_INV = 1, OP_POLYMUL = 2, OP_COUNT = 3 };
 
@@ -28,8 +31,9 @@ PassPlan plan_for(int op, unsigned log2n);
 PassPlan plan_for(int op, unsigned log2n, size_t batch_words);
 // Returns false if (op, log2n, logc) is not a valid split.
 bool plan_set(int op, unsigned log2n, unsigned logc);
-// Small-batch plan: logc = 0 removes it; ebx in {2, 4}; ebx = 2 needs
-// 5 <= logc <= 12. Returns false for an invalid split.
+// Small-batch plan: logc = 0 removes it; ebx in {2, 4}. ebx = 4 takes the
+// throughput splits; ebx = 2 needs 5 <= logc <= 12 and a column radix of
+// 2^2..2^7 (2^1 with >= 256 columns). Returns false for an invalid split.
 bool plan_small_set(int op, unsigned log2n, unsigned logc, unsigned ebx);
 bool plan_small_get(int op, unsigned log2n, unsigned* logc, unsigned* ebx);
 void plan_small_threshold_set(size_t words);

@@ -104,9 +104,15 @@ def tune(log2ns, words=1 << 25, device="cuda", verbose=True):
 
 
 def small_candidates(log2n: int):
-    """(logc, words_per_thread) pairs of the small-batch plans."""
+    """(logc, words_per_thread) pairs of the small-batch plans: the throughput
+    splits with 16 words per thread, and with 4 words per thread rows of
+    2^5..2^12 words over a column pass of 2^2..2^7 rows (2 rows only with
+    >= 2^8 columns)."""
     out = [(c, 16) for c in candidates(log2n)]
-    out += [(c, 4) for c in candidates(log2n) if 5 <= c <= 12]
+    for c in range(5, min(log2n, 12) + 1):
+        r = log2n - c
+        if r <= 7 and not (r == 1 and c < 8):
+            out.append((c, 4))
     return out
 
 

@@ -199,9 +199,13 @@ def test_small_plan_table(L):
         assert L.pm_tune_get_small(L.OP_NTT_FWD, 14) == (10, 4)
         L.pm_tune_set_small(L.OP_POLYMUL, 13, 13, 16)
         assert L.pm_tune_get_small(L.OP_POLYMUL, 13) == (13, 16)
-        # 4 words per thread: rows of 2^5..2^12 only; the usual split limits still hold
-        for bad in [(14, 14, 4), (4, 4, 4), (16, 10, 4), (12, 7, 16), (10, 10, 8)]:
+        # 4 words per thread: rows of 2^5..2^12, column passes of 2^2..2^7 rows
+        # (2 rows only with >= 256 columns); 16 words: the throughput splits
+        for bad in [(14, 14, 4), (4, 4, 4), (17, 9, 4), (8, 7, 4), (12, 7, 16), (10, 10, 8)]:
             assert lib.pm_tune_set_small(L.OP_NTT_FWD, *bad) == L.PM_EINVAL, bad
+        for good in [(16, 10, 4), (13, 6, 4), (9, 5, 4), (9, 8, 4), (17, 10, 4)]:
+            assert lib.pm_tune_set_small(L.OP_NTT_INV, *good) == 0, good
+            assert L.pm_tune_get_small(L.OP_NTT_INV, good[0]) == good[1:]
         # a small plan changes the workspace only for batches under the threshold
         N = 1 << 13
         L.pm_tune_set_small(L.OP_POLYMUL, 13, 9, 4)

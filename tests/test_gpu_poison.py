@@ -3,7 +3,8 @@ exchange first fills the row's LDS with words above every modulus) gives
 bit-exact oracle results: no row kernel reads an LDS slot that the current
 exchange did not write (a missing barrier or an indexing error would show up
 as a mismatch). Called through the debug library's own C ABI, for every
-row mode and both row geometries, single- and two-pass splits, and the
+row mode and both row geometries, single- and two-pass splits, the four-word
+column pass from 2^4 to 2^7 rows (odd and even depths), and the
 batched-jobs kernels."""
 import ctypes
 import os
@@ -50,9 +51,9 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
-@pytest.mark.parametrize("small", [False, True], ids=["16-word", "4-word"])
+@pytest.mark.parametrize("geo", ["16-word", "4-word", "4-word-deep"])
 @pytest.mark.parametrize("log2n", [6, 10, 12, 13, 14, 16])
-def test_poisoned_lds_parity(env, log2n, small):
+def test_poisoned_lds_parity(env, log2n, geo):
     import torch
     L, P = env
     N, limbs, polys = 1 << log2n, 2, 2
@@ -62,11 +63,16 @@ def test_poisoned_lds_parity(env, log2n, small):
     a, b = operands(N, qs, polys, request=2500 + log2n)
     want = oracle_polymul(a, b, qs, N, fw_o, iv_o)
     qarr = (ctypes.c_uint64 * limbs)(*qs)
+    small = geo != "16-word"
     try:
         if small:
-            if log2n < 5:
-                pytest.skip("no 4-word rows below 2^5")
-            logc = log2n if log2n <= 12 else max(8, log2n - 4)
+            if geo == "4-word":
+                logc = log2n if log2n <= 12 else max(8, log2n - 4)
+            else:
+                # the deepest column pass: 2^7 rows, or rows of 2^5 words
+                logc = max(5, log2n - 7)
+                if log2n - logc < 2:
+                    pytest.skip("no four-word column pass for N = 2^%d" % log2n)
             for op in (0, 1, 2):
                 _check(P, P.pm_tune_set_small(op, log2n, min(logc, 12), 4), "tune")
             P.pm_tune_set_small_batch(1 << 22)

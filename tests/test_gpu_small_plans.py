@@ -1,7 +1,9 @@
-"""Small-batch pass plans (4 words per thread in the row pass, shorter rows):
+"""Small-batch pass plans (4 words per thread in both passes, shorter rows):
 bit-exact parity with the CPU oracle for every valid (N, row length) under the
 4-word geometry, on 64- and 32-bit words, and the threshold that selects them
 (checked through the names of the kernels the library launched)."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -40,13 +42,48 @@ def _eq(got, want, what):
 
 
 def small_plans():
+    """Every (log2 N, log2 C) of the 4-word geometry: rows of 2^5..2^12 words,
+    column passes of 2^2..2^7 rows (four words per thread) or of 2 rows with
+    one thread per column (>= 256 columns)."""
     out = []
     for log2n in range(5, 18):
         for logc in range(5, min(log2n, 12) + 1):
-            if log2n - logc > 5 or (logc < log2n and logc < 8):
+            logr = log2n - logc
+            if logr > 7 or (logr == 1 and logc < 8):
                 continue
             out.append((log2n, logc))
     return out
+
+
+@functools.lru_cache(maxsize=None)
+def _case64(log2n):
+    """Operands and oracle results for N = 2^log2n, two 60-bit limbs, two pairs."""
+    N, limbs, polys = 1 << log2n, 2, 2
+    from paper_2209_01290_amd import lib
+    qs = lib.pm_ntt_primes(N, limbs)
+    fw_o, iv_o = oracle_tables(qs, N)
+    a, b = operands(N, qs, polys, request=1500 + log2n)
+    return (qs, a, b, oracle_ntt_fwd(a, qs, fw_o), oracle_ntt_inv(a, qs, iv_o),
+            oracle_polymul(a, b, qs, N, fw_o, iv_o), oracle_polymul(a, a, qs, N, fw_o, iv_o))
+
+
+@functools.lru_cache(maxsize=None)
+def _case32(log2n):
+    """Operands and oracle results for N = 2^log2n, two 30-bit limbs, two pairs."""
+    N, limbs, polys = 1 << log2n, 2, 2
+    from paper_2209_01290_amd import lib
+    qs = lib.pm_ntt_primes(N, limbs, 30)
+    fw_o, iv_o = oracle_tables(qs, N)
+    a, b = operands(N, qs, polys, request=1600 + log2n)
+    return (qs, a, b, oracle_ntt_fwd(a, qs, fw_o), oracle_ntt_inv(a, qs, iv_o),
+            oracle_polymul(a, b, qs, N, fw_o, iv_o))
+
+
+def _col_kernel(log2n, logc, inv=False):
+    logr = log2n - logc
+    if logr == 0:
+        return None
+    return ("colq" if logr >= 2 else "col") + ("_inv_r%d" if inv else "_fwd_r%d") % logr
 
 
 def _install(L, log2n, logc, wpt=4):
@@ -66,31 +103,28 @@ def test_small_plan_u64(L, small, log2n, logc):
     import torch
     N, limbs, polys = 1 << log2n, 2, 2
     _install(L, log2n, logc)
-    qs = L.pm_ntt_primes(N, limbs)
-    fw_o, iv_o = oracle_tables(qs, N)
+    qs, a, b, want_fwd, want_inv, want, want_sq = _case64(log2n)
     prm = L.Params(N, limbs, primes=qs)
-    a, b = operands(N, qs, polys, request=1500 + 20 * log2n + logc)
     L.pm_prof_read(reset=True)
     L.pm_prof_enable(True)
     try:
         x = L.to_device(a)
         L.pm_ntt_fwd(x, N, limbs, polys, qs, prm.psi_br)
         _sync()
-        _eq(L.to_host(x).reshape(a.shape), oracle_ntt_fwd(a, qs, fw_o), "fwd N=%d c=%d" % (N, logc))
+        _eq(L.to_host(x).reshape(a.shape), want_fwd, "fwd N=%d c=%d" % (N, logc))
         y = L.to_device(a)
         L.pm_ntt_inv(y, N, limbs, polys, qs, prm.psi_inv_br)
         _sync()
-        _eq(L.to_host(y).reshape(a.shape), oracle_ntt_inv(a, qs, iv_o), "inv N=%d c=%d" % (N, logc))
+        _eq(L.to_host(y).reshape(a.shape), want_inv, "inv N=%d c=%d" % (N, logc))
         da, db = L.to_device(a), L.to_device(b)
         dc = torch.empty_like(da)
         L.pm_polymul(da, db, dc, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, _ws(L, N, limbs, polys))
         _sync()
-        want = oracle_polymul(a, b, qs, N, fw_o, iv_o)
         _eq(L.to_host(dc).reshape(a.shape), want, "polymul N=%d c=%d" % (N, logc))
         # a = b (the 4-word geometry runs the product with b = a) and c = a
         L.pm_polymul(da, da, da, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, None)
         _sync()
-        _eq(L.to_host(da).reshape(a.shape), oracle_polymul(a, a, qs, N, fw_o, iv_o), "square N=%d c=%d" % (N, logc))
+        _eq(L.to_host(da).reshape(a.shape), want_sq, "square N=%d c=%d" % (N, logc))
         # the fused product keeps the 16-word rows under the same split
         df = torch.empty_like(db)
         L.pm_polymul_fused(L.to_device(a), db, df, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br,
@@ -102,6 +136,8 @@ def test_small_plan_u64(L, small, log2n, logc):
     names = L.pm_prof_read(reset=True)
     assert "row_fwd_c%ds" % logc in names and "row_mul_c%ds" % logc in names, sorted(names)
     assert "row_fmul_c%d" % logc in names
+    if log2n > logc:
+        assert _col_kernel(log2n, logc) in names and _col_kernel(log2n, logc, True) in names, sorted(names)
 
 
 @pytest.mark.parametrize("log2n,logc", [p for p in small_plans() if p[0] in (10, 12, 14, 16, 17)],
@@ -110,22 +146,24 @@ def test_small_plan_u32(L, small, log2n, logc):
     import torch
     N, limbs, polys = 1 << log2n, 2, 2
     _install(L, log2n, logc)
-    qs = L.pm_ntt_primes(N, limbs, 30)
-    fw_o, iv_o = oracle_tables(qs, N)
+    qs, a, b, want_fwd, want_inv, want = _case32(log2n)
     prm = L.Params32(N, limbs, primes=qs)
-    a, b = operands(N, qs, polys, request=1600 + 20 * log2n + logc)
     x = L.to_device32(a)
     L.pm_ntt_fwd_u32(x, N, limbs, polys, qs, prm.psi_br)
     _sync()
-    _eq(L.to_host32(x).reshape(a.shape), oracle_ntt_fwd(a, qs, fw_o), "fwd32 N=%d c=%d" % (N, logc))
+    _eq(L.to_host32(x).reshape(a.shape), want_fwd, "fwd32 N=%d c=%d" % (N, logc))
     L.pm_ntt_inv_u32(x, N, limbs, polys, qs, prm.psi_inv_br)
     _sync()
     _eq(L.to_host32(x).reshape(a.shape), a, "roundtrip32 N=%d c=%d" % (N, logc))
+    y = L.to_device32(a)
+    L.pm_ntt_inv_u32(y, N, limbs, polys, qs, prm.psi_inv_br)
+    _sync()
+    _eq(L.to_host32(y).reshape(a.shape), want_inv, "inv32 N=%d c=%d" % (N, logc))
     da, db = L.to_device32(a), L.to_device32(b)
     dc = torch.empty_like(da)
     L.pm_polymul_u32(da, db, dc, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, _ws(L, N, limbs, polys, True))
     _sync()
-    _eq(L.to_host32(dc).reshape(a.shape), oracle_polymul(a, b, qs, N, fw_o, iv_o), "polymul32 N=%d c=%d" % (N, logc))
+    _eq(L.to_host32(dc).reshape(a.shape), want, "polymul32 N=%d c=%d" % (N, logc))
 
 
 def test_threshold_selects_plan(L, small):
