@@ -258,13 +258,20 @@ int pm_tune_get(int op, unsigned log2n);   /* current logc, or PM_EINVAL */
  * rows), 16 any valid split; logc = 0 removes the plan. A call over
  * N * limbs * polys_per_limb <= pm_tune_get_small_batch() words uses the
  * small-batch plan of its (op, N) if one is installed; the threshold is 0
- * (no small-batch plans used) until pm_tune_set_small_batch sets it. Results
- * are identical under every plan; workspace sizes follow the plan in use.
+ * (no small-batch plans used) until pm_tune_set_small_batch sets it.
+ * pm_tune_set_small_limit sets a limit for one (op, N) that replaces the
+ * global threshold there (the batch size up to which that plan wins varies
+ * with N); max_words = 0 restores the global threshold;
+ * pm_tune_get_small_limit returns 0 when none is set (or for an invalid
+ * op / N). Results are identical under every plan; workspace sizes follow
+ * the plan in use.
  */
 int pm_tune_set_small(int op, unsigned log2n, unsigned logc, unsigned words_per_thread);
 int pm_tune_get_small(int op, unsigned log2n, unsigned *logc, unsigned *words_per_thread);
 int pm_tune_set_small_batch(size_t max_words);
 size_t pm_tune_get_small_batch(void);
+int pm_tune_set_small_limit(int op, unsigned log2n, size_t max_words);
+size_t pm_tune_get_small_limit(int op, unsigned log2n);
 
 /* ------------------------------------------------------------- kernel timing
  * While enabled, every kernel the library launches is bracketed by two HIP

@@ -14,6 +14,8 @@ std::atomic<uint32_t> g_logc[OP_COUNT][PM_MAX_LOG2N + 1];
 // small-batch plans: logc | ebx << 8 per (op, log2n); 0 = none installed
 std::atomic<uint32_t> g_small[OP_COUNT][PM_MAX_LOG2N + 1];
 std::atomic<size_t> g_small_words{0};
+// per (op, log2n) batch limit of the small-batch plan; 0 = g_small_words
+std::atomic<size_t> g_small_limit[OP_COUNT][PM_MAX_LOG2N + 1];
 
 bool valid_split(unsigned log2n, unsigned logc) {
   if (logc > log2n || logc > PM_MAX_LOGC || log2n - logc > PM_MAX_LOGR) return false;
@@ -71,6 +73,17 @@ bool plan_small_get(int op, unsigned log2n, unsigned* logc, unsigned* ebx) {
 void plan_small_threshold_set(size_t words) { g_small_words.store(words); }
 size_t plan_small_threshold() { return g_small_words.load(); }
 
+bool plan_small_limit_set(int op, unsigned log2n, size_t words) {
+  if (op < 0 || op >= OP_COUNT || log2n < 1 || log2n > PM_MAX_LOG2N) return false;
+  g_small_limit[op][log2n].store(words);
+  return true;
+}
+
+size_t plan_small_limit(int op, unsigned log2n) {
+  if (op < 0 || op >= OP_COUNT || log2n < 1 || log2n > PM_MAX_LOG2N) return 0;
+  return g_small_limit[op][log2n].load();
+}
+
 PassPlan plan_for(int op, unsigned log2n) {
   uint32_t logc = g_logc[op][log2n].load();
   if (logc == 0) logc = default_logc(op, log2n);
@@ -83,7 +96,8 @@ PassPlan plan_for(int op, unsigned log2n) {
 }
 
 PassPlan plan_for(int op, unsigned log2n, size_t batch_words) {
-  if (batch_words <= g_small_words.load()) {
+  const size_t limit = g_small_limit[op][log2n].load();
+  if (batch_words <= (limit ? limit : g_small_words.load())) {
     const uint32_t v = g_small[op][log2n].load();
     if (v) {
       PassPlan p;
@@ -128,3 +142,9 @@ extern "C" int pm_tune_set_small_batch(size_t max_words) {
 }
 
 extern "C" size_t pm_tune_get_small_batch(void) { return pm::plan_small_threshold(); }
+
+extern "C" int pm_tune_set_small_limit(int op, unsigned log2n, size_t max_words) {
+  return pm::plan_small_limit_set(op, log2n, max_words) ? PM_OK : PM_EINVAL;
+}
+
+extern "C" size_t pm_tune_get_small_limit(int op, unsigned log2n) { return pm::plan_small_limit(op, log2n); }

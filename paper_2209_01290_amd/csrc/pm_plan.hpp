@@ -27,7 +27,8 @@ struct PassPlan {
 PassPlan plan_for(int op, unsigned log2n);
 // The plan for a call over batch_words = N * limbs * polys words: the
 // small-batch plan of (op, log2n) if one is installed and batch_words is at
-// most the small-batch threshold, else the throughput plan.
+// most its limit (the per-(op, log2n) limit if set, else the global
+// small-batch threshold), else the throughput plan.
 PassPlan plan_for(int op, unsigned log2n, size_t batch_words);
 // Returns false if (op, log2n, logc) is not a valid split.
 bool plan_set(int op, unsigned log2n, unsigned logc);
@@ -38,5 +39,9 @@ bool plan_small_set(int op, unsigned log2n, unsigned logc, unsigned ebx);
 bool plan_small_get(int op, unsigned log2n, unsigned* logc, unsigned* ebx);
 void plan_small_threshold_set(size_t words);
 size_t plan_small_threshold();
+// Per (op, log2n) batch limit of the small-batch plan (0 = the global
+// threshold above); false for an invalid (op, log2n).
+bool plan_small_limit_set(int op, unsigned log2n, size_t words);
+size_t plan_small_limit(int op, unsigned log2n);
 
 }  // namespace pm

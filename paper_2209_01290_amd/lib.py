@@ -74,6 +74,8 @@ def load():
                                         ctypes.POINTER(ctypes.c_uint)]),
             "pm_tune_set_small_batch": (i32, [sz]),
             "pm_tune_get_small_batch": (sz, []),
+            "pm_tune_set_small_limit": (i32, [i32, ctypes.c_uint, sz]),
+            "pm_tune_get_small_limit": (sz, [i32, ctypes.c_uint]),
             "pm_ntt_primes": (sz, [u64, ctypes.c_uint, sz, u64p]),
             "pm_find_psi": (u64, [u64, sz]),
             "pm_make_tables": (i32, [u64, sz, u64, u64p, u64p]),
@@ -118,7 +120,8 @@ def exported_symbols():
             "pm_polymul_u32_workspace_bytes",
             "pm_make_tables_u32", "pm_ntt_fwd_il", "pm_ntt_inv_il", "pm_polymul_il",
             "pm_polymul_il_workspace_bytes", "pm_tune_set_small", "pm_tune_get_small",
-            "pm_tune_set_small_batch", "pm_tune_get_small_batch"]
+            "pm_tune_set_small_batch", "pm_tune_get_small_batch", "pm_tune_set_small_limit",
+            "pm_tune_get_small_limit"]
 
 
 def _check(rc: int, func: str):
@@ -384,11 +387,21 @@ def pm_tune_get_small_batch():
     return int(load().pm_tune_get_small_batch())
 
 
+def pm_tune_set_small_limit(op, log2n, max_words):
+    """Batch limit (words) of the small-batch plan of (op, N); 0 = the global threshold."""
+    _check(load().pm_tune_set_small_limit(op, log2n, max_words), "pm_tune_set_small_limit")
+
+
+def pm_tune_get_small_limit(op, log2n):
+    return int(load().pm_tune_get_small_limit(op, log2n))
+
+
 def apply_tune_db(path=None):
     """Install the pass plans of an autotuner database (see tune.py; default:
     $PM_TUNE_DB, else the packaged MI355X database): the
     throughput plans ("choices") and, if present, the small-batch plans
-    ("small": {"max_words": W, "choices": {op: {log2n: [logc, words_per_thread]}}});
+    ("small": {"max_words": W, "choices": {op: {log2n: [logc, words_per_thread]}},
+    "limits": {op: {log2n: words}}}, the limits replacing W for their (op, N));
     returns the number of entries applied, 0 if the file does not exist."""
     import json
     if path is None:
@@ -408,6 +421,10 @@ def apply_tune_db(path=None):
         for name, table in small.get("choices", {}).items():
             for log2n, (logc, wpt) in table.items():
                 pm_tune_set_small(ops[name], int(log2n), int(logc), int(wpt))
+                n += 1
+        for name, table in small.get("limits", {}).items():
+            for log2n, words in table.items():
+                pm_tune_set_small_limit(ops[name], int(log2n), int(words))
                 n += 1
         pm_tune_set_small_batch(int(small["max_words"]))
     return n

@@ -12,11 +12,14 @@ with pm_tune_set and writes the choices to a JSON database:
 Small-batch plans (--small): for a single transform or product per call
 (one limb, one polynomial) it times every split with 16 and with 4 words per
 thread (device time per call, 20 calls captured in one HIP graph and
-replayed), keeps the fastest per (operation, N), and finds the largest batch
-(in words) at which the small-batch plan still beats the throughput plan,
-doubling the batch at N = 2^12 and 2^16:
+replayed), keeps the fastest per (operation, N), and finds for each
+(operation, N >= 2^8) the largest batch (in words) at which the small-batch
+plan still beats the throughput plan, doubling the batch from one
+polynomial; the smallest of these limits is the global threshold W for the
+other sizes:
 
     "small": {"max_words": W, "choices": {"polymul": {"16": [logc, words_per_thread]}, ...},
+              "limits": {"polymul": {"16": words, ...}, ...},
               "latency_us": {...}, "crossover_us": {...}}
 
 Usage on a GPU:  python -m paper_2209_01290_amd.tune [--out FILE] [--log2n 12-17] [--small]
@@ -147,12 +150,19 @@ def _calls(lib, name, prm, N, polys, da, db, dc, x, ws):
     return lambda: lib.pm_ntt_inv(x, N, 1, polys, prm.q, prm.psi_inv_br)
 
 
+LIMIT_MIN_LOG2N = 8            # per-N limits for N >= 2^8; the global threshold below
+LIMIT_MAX_WORDS = 1 << 22      # largest batch the limit search tries (32 MiB per operand)
+
+
 def tune_small(log2ns, device="cuda", verbose=True):
     import torch
     from . import lib, synth
     lib.load()
     dev = torch.device(device)
     lib.pm_tune_set_small_batch(1 << 40)          # every call below is "small" while tuning
+    for op in OPS.values():
+        for n in range(1, 18):
+            lib.pm_tune_set_small_limit(op, n, 0)
     choices = {k: {} for k in OPS}
     lat = {k: {} for k in OPS}
     for log2n in log2ns:
@@ -180,22 +190,24 @@ def tune_small(log2ns, device="cuda", verbose=True):
             if verbose:
                 print("[tune-small] %-8s N=2^%-2d -> %s  %.2f us  %s" % (name, log2n, best, best_us,
                                                                     lat[name][str(log2n)]), flush=True)
-    # crossover: the largest batch at which the small plan still wins (forward NTT and product)
+    # Per-(op, N) limit: the largest batch (polynomials doubled from 1, up to
+    # LIMIT_MAX_WORDS words) at which the small plan still beats the
+    # throughput plan; the search stops after two sizes in a row lost.
     cross = {}
-    max_words = None
-    for log2n in (12, 16):
-        if str(log2n) not in choices["polymul"]:
+    limits = {k: {} for k in OPS}
+    for log2n in log2ns:
+        if log2n < LIMIT_MIN_LOG2N or str(log2n) not in choices["polymul"]:
             continue
         N = 1 << log2n
         prm = lib.Params(N, 1, device=dev)
-        for name in ("ntt_fwd", "polymul"):
-            op = OPS[name]
+        pmax = LIMIT_MAX_WORDS // N
+        a, b = synth.operands(synth.SEED_BASE + 19, prm.q, pmax, N)
+        da_all, db_all = lib.to_device(a, dev), lib.to_device(b, dev)
+        for name, op in OPS.items():
             keep = lib.pm_tune_get_small(op, log2n)
-            won = 0
-            for lp in range(0, 9):
-                polys = 1 << lp
-                a, b = synth.operands(synth.SEED_BASE + 19, prm.q, polys, N)
-                da, db = lib.to_device(a, dev), lib.to_device(b, dev)
+            won, lost, polys = 0, 0, 1
+            while polys <= pmax and lost < 2:
+                da, db = da_all[:, :polys].contiguous(), db_all[:, :polys].contiguous()
                 dc = torch.empty_like(da)
                 x = da.clone()
                 t = {}
@@ -207,13 +219,19 @@ def tune_small(log2ns, device="cuda", verbose=True):
                 lib.pm_tune_set_small(op, log2n, *keep)
                 cross["%s/%d/%d" % (name, log2n, polys)] = t
                 if t["small"] < t["throughput"]:
-                    won = N * polys
-            max_words = won if max_words is None else min(max_words, won)
+                    won, lost = N * polys, 0
+                else:
+                    lost += 1
+                polys *= 2
+            limits[name][str(log2n)] = won
+            lib.pm_tune_set_small_limit(op, log2n, won)
             if verbose:
-                print("[tune-small] crossover %s N=2^%d: small wins up to %d words" % (name, log2n, won), flush=True)
-    max_words = max_words or 0
+                print("[tune-small] limit %-8s N=2^%-2d: small plan up to %d words" % (name, log2n, won), flush=True)
+    # the global threshold (for N without a limit): the smallest limit
+    max_words = min((w for t in limits.values() for w in t.values()), default=0)
     lib.pm_tune_set_small_batch(max_words)
-    return {"max_words": max_words, "choices": choices, "latency_us": lat, "crossover_us": cross}
+    return {"max_words": max_words, "choices": choices, "limits": limits, "latency_us": lat,
+            "crossover_us": cross}
 
 
 def main():

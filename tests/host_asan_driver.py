@@ -35,6 +35,9 @@ L.pm_tune_set_small.argtypes = [i32, uint, uint, uint]
 L.pm_tune_get_small.argtypes = [i32, uint, ctypes.POINTER(uint), ctypes.POINTER(uint)]
 L.pm_tune_set_small_batch.argtypes = [sz]
 L.pm_tune_get_small_batch.restype = sz
+L.pm_tune_set_small_limit.argtypes = [i32, uint, sz]
+L.pm_tune_get_small_limit.argtypes = [i32, uint]
+L.pm_tune_get_small_limit.restype = sz
 
 
 class Job(ctypes.Structure):
@@ -108,6 +111,9 @@ for op in (0, 1, 2):
         L.pm_tune_get_small(op, n, ctypes.byref(a), ctypes.byref(b))
         L.pm_tune_set(op, n, 0) if 1 <= n <= 17 else None
         L.pm_tune_set_small(op, n, 0, 0)
+        L.pm_tune_set_small_limit(op, n, 1 << 20)
+        L.pm_tune_get_small_limit(op, n)
+        L.pm_tune_set_small_limit(op, n, 0)
 assert L.pm_tune_get_small(5, 3, None, None) == EINVAL
 L.pm_tune_set_small_batch(1 << 20)
 assert L.pm_tune_get_small_batch() == 1 << 20

@@ -124,14 +124,20 @@ def test_tune_db_applies(L, tmp_path):
                 assert tuple(plan) in tune.small_candidates(int(log2n))
         n = L.apply_tune_db()
         assert n == sum(len(t) for t in shipped["choices"].values()) + \
-            sum(len(t) for t in shipped["small"]["choices"].values())
+            sum(len(t) for t in shipped["small"]["choices"].values()) + \
+            sum(len(t) for t in shipped["small"].get("limits", {}).values())
         assert L.pm_tune_get_small_batch() == shipped["small"]["max_words"] > 0
         assert L.pm_tune_get_small(L.OP_POLYMUL, 16) == tuple(shipped["small"]["choices"]["polymul"]["16"])
+        ops = {"polymul": L.OP_POLYMUL, "ntt_fwd": L.OP_NTT_FWD, "ntt_inv": L.OP_NTT_INV}
+        for name, table in shipped["small"].get("limits", {}).items():
+            for log2n, words in table.items():
+                assert L.pm_tune_get_small_limit(ops[name], int(log2n)) == words
     finally:
         for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
             for n in range(1, 18):
                 L.pm_tune_set(op, n, 0)
                 L.pm_tune_set_small(op, n, 0, 0)
+                L.pm_tune_set_small_limit(op, n, 0)
         L.pm_tune_set_small_batch(0)
 
 
@@ -213,8 +219,21 @@ def test_small_plan_table(L):
         L.pm_tune_set_small_batch(N)
         assert L.pm_polymul_workspace_bytes(N, 1, 1) == N * 8
         assert L.pm_polymul_workspace_bytes(N, 1, 2) == 0
+        # a per-(op, N) limit replaces the global threshold for that (op, N) only
+        L.pm_tune_set_small_limit(L.OP_POLYMUL, 13, 4 * N)
+        assert L.pm_tune_get_small_limit(L.OP_POLYMUL, 13) == 4 * N
+        assert L.pm_tune_get_small_limit(L.OP_NTT_FWD, 13) == 0
+        assert L.pm_polymul_workspace_bytes(N, 1, 4) == 4 * N * 8
+        assert L.pm_polymul_workspace_bytes(N, 2, 2) == 4 * N * 8
+        assert L.pm_polymul_workspace_bytes(N, 1, 8) == 0
+        L.pm_tune_set_small_limit(L.OP_POLYMUL, 13, 0)
+        assert L.pm_polymul_workspace_bytes(N, 1, 4) == 0 and L.pm_polymul_workspace_bytes(N, 1, 1) == N * 8
+        for bad in [(3, 13), (-1, 13), (L.OP_POLYMUL, 0), (L.OP_POLYMUL, 18)]:
+            assert lib.pm_tune_set_small_limit(bad[0], bad[1], 1) == L.PM_EINVAL, bad
+            assert L.pm_tune_get_small_limit(*bad) == 0
     finally:
         for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
             for n in range(1, 18):
                 L.pm_tune_set_small(op, n, 0, 0)
+                L.pm_tune_set_small_limit(op, n, 0)
         L.pm_tune_set_small_batch(0)

@@ -28,6 +28,7 @@ def small(L):
     for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
         for n in range(1, 18):
             L.pm_tune_set_small(op, n, 0, 0)
+            L.pm_tune_set_small_limit(op, n, 0)
     L.pm_tune_set_small_batch(0)
 
 
@@ -189,3 +190,13 @@ def test_threshold_selects_plan(L, small):
         _eq(L.to_host(x).reshape(1, polys, N), want[:, :polys], "threshold polys=%d" % polys)
     assert L.pm_tune_get_small(L.OP_NTT_FWD, 12) == (12, 4)
     assert L.pm_tune_get_small_batch() == 4 * N
+    # a per-N limit above the global threshold: 8 polynomials now take the small plan
+    L.pm_tune_set_small_limit(L.OP_NTT_FWD, 12, 8 * N)
+    x = L.to_device(a)
+    L.pm_prof_read(reset=True)
+    L.pm_prof_enable(True)
+    L.pm_ntt_fwd(x, N, limbs, 8, qs, prm.psi_br)
+    L.pm_prof_enable(False)
+    _sync()
+    assert list(L.pm_prof_read(reset=True)) == ["row_fwd_c12s"]
+    _eq(L.to_host(x).reshape(1, 8, N), want, "limit polys=8")
