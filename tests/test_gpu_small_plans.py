@@ -165,6 +165,44 @@ def test_small_plan_u32(L, small, log2n, logc):
     L.pm_polymul_u32(da, db, dc, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, _ws(L, N, limbs, polys, True))
     _sync()
     _eq(L.to_host32(dc).reshape(a.shape), want, "polymul32 N=%d c=%d" % (N, logc))
+    # the fused product (16-word rows) over the same column pass
+    df = torch.empty_like(da)
+    L.pm_polymul_fused_u32(da, db, df, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br,
+                           _ws(L, N, limbs, polys, True))
+    _sync()
+    _eq(L.to_host32(df).reshape(a.shape), want, "fused32 N=%d c=%d" % (N, logc))
+
+
+# moduli outside 34..61 bits take the generic Barrett instantiation
+# (run-time word window and final shift) in every kernel, k_colq included
+ANY_KIND = [(62, 16, 9), (62, 17, 10), (62, 13, 6), (33, 12, 5), (20, 11, 8), (31, 15, 8)]
+
+
+@pytest.mark.parametrize("bits,log2n,logc", ANY_KIND, ids=lambda v: str(v))
+def test_small_plan_other_moduli(L, small, bits, log2n, logc):
+    import torch
+    N, limbs, polys = 1 << log2n, 2, 2
+    _install(L, log2n, logc)
+    qs = L.pm_ntt_primes(N, limbs, bits)
+    assert len(qs) == limbs
+    fw_o, iv_o = oracle_tables(qs, N)
+    prm = L.Params(N, limbs, primes=qs)
+    a, b = operands(N, qs, polys, request=1800 + bits)
+    x = L.to_device(a)
+    L.pm_ntt_fwd(x, N, limbs, polys, qs, prm.psi_br)
+    y = L.to_device(a)
+    L.pm_ntt_inv(y, N, limbs, polys, qs, prm.psi_inv_br)
+    da, db = L.to_device(a), L.to_device(b)
+    dc, df = torch.empty_like(da), torch.empty_like(da)
+    L.pm_polymul(da, db, dc, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, _ws(L, N, limbs, polys))
+    L.pm_polymul_fused(da, db, df, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, _ws(L, N, limbs, polys))
+    _sync()
+    what = "q%d N=2^%d c=%d" % (bits, log2n, logc)
+    _eq(L.to_host(x).reshape(a.shape), oracle_ntt_fwd(a, qs, fw_o), "fwd " + what)
+    _eq(L.to_host(y).reshape(a.shape), oracle_ntt_inv(a, qs, iv_o), "inv " + what)
+    want = oracle_polymul(a, b, qs, N, fw_o, iv_o)
+    _eq(L.to_host(dc).reshape(a.shape), want, "polymul " + what)
+    _eq(L.to_host(df).reshape(a.shape), want, "fused " + what)
 
 
 def test_threshold_selects_plan(L, small):
