@@ -315,6 +315,14 @@ def pm_polymul_jobs_workspace_bytes_raw(jobs_ptr, njobs):
     return int(load().pm_polymul_jobs_workspace_bytes(ctypes.cast(jobs_ptr, ctypes.POINTER(Job)), njobs))
 
 
+def pm_polymul_raw(a_ptr, b_ptr, c_ptr, N, limbs, polys_per_limb, q_arr, psi_br_ptr, psi_inv_br_ptr,
+                   workspace_ptr, stream):
+    """As pm_polymul, for raw device pointers, a ctypes uint64 array of at
+    least `limbs` moduli and a raw stream handle (no tensor checks)."""
+    _check(load().pm_polymul(a_ptr, b_ptr, c_ptr, N, limbs, polys_per_limb, q_arr, psi_br_ptr, psi_inv_br_ptr,
+                             workspace_ptr, stream), "pm_polymul")
+
+
 def pm_polymul_jobs_raw(jobs_ptr, njobs, workspace_ptr, workspace_bytes, stream):
     """As pm_polymul_jobs, for a host array of pm_job records at jobs_ptr and raw
     device / stream handles."""

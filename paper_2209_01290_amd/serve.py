@@ -28,6 +28,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import ctypes
 import gc
 import json
 import time
@@ -260,11 +261,15 @@ class Engine:
 
 class GpuExecutor:
     """Runs batches with pm_polymul_jobs: outputs in a device arena, one fixed
-    workspace per stream, operand pools and tables resident."""
+    workspace per stream, operand pools and tables resident. A batch of one
+    request (the common case below saturation) runs as one pm_polymul over
+    its limbs instead (single_request_path): its operands, tables and arena
+    slot are contiguous [limbs][N] blocks, and pm_polymul takes the tuned
+    small-batch plan when the request is small enough to be latency-bound."""
 
     def __init__(self, budget_bytes: int, streams: int = 3, pool: int = 4, max_limbs: int = 60,
                  log2ns=workloads.SERVE_LOG2N, device="cuda", seed: int = SEED,
-                 ws_bytes_per_stream: int = 2 << 30):
+                 ws_bytes_per_stream: int = 2 << 30, single_request_path: bool = True):
         import torch
         from . import lib, synth
         self.torch, self.lib = torch, lib
@@ -310,6 +315,9 @@ class GpuExecutor:
                 rows["a"] = np.uint64(a[p].data_ptr()) + lidx
                 rows["b"] = np.uint64(b[p].data_ptr()) + lidx
                 self.rows[(log2n, p)] = rows
+        self.single_request_path = single_request_path
+        self.qarr = {n: (ctypes.c_uint64 * max_limbs)(*self.tables.get(n, max_limbs).q[:max_limbs])
+                     for n in log2ns}
         torch.cuda.synchronize()
 
     def budget(self):
@@ -341,10 +349,20 @@ class GpuExecutor:
         return self.arena_t[off: off + r.limbs * N].view(r.limbs, N)
 
     def launch(self, batch, k):
-        jobs = np.concatenate([self.job_rows(r) for r in batch])
         i = k % len(self.streams)
         s, ws = self.streams[i], self.ws[i]
-        self.lib.pm_polymul_jobs_raw(jobs.ctypes.data, len(jobs), ws.data_ptr(), self.ws_bytes, s.cuda_stream)
+        if len(batch) == 1 and self.single_request_path:
+            r = batch[0]
+            a, b = self.inputs[r.log2n]
+            p = r.rid % self.pool
+            prm = self.tables.get(r.log2n, self.max_limbs)
+            self.lib.pm_polymul_raw(a[p].data_ptr(), b[p].data_ptr(), self.base + r.alloc[0], 1 << r.log2n,
+                                    r.limbs, 1, self.qarr[r.log2n], prm.psi_br.data_ptr(),
+                                    prm.psi_inv_br.data_ptr(), ws.data_ptr(), s.cuda_stream)
+        else:
+            jobs = np.concatenate([self.job_rows(r) for r in batch])
+            self.lib.pm_polymul_jobs_raw(jobs.ctypes.data, len(jobs), ws.data_ptr(), self.ws_bytes,
+                                         s.cuda_stream)
         ev = self.torch.cuda.Event()
         ev.record(s)
         return (ev, s)

@@ -58,3 +58,31 @@ def test_small_budget_queues_and_completes(ex):
     st = eng.run(trace)
     assert st["completed"] == 120 and st["max_queue"] > 1
     assert st["arena_peak_bytes"] <= 2 * one
+
+
+def test_single_request_batches_match_jobs_path(ex):
+    """Below saturation most batches hold one request, which runs as one
+    pm_polymul (small-batch plans installed); every result equals the same
+    request through pm_polymul_jobs alone."""
+    from paper_2209_01290_amd import lib
+    trace = workloads.serving_requests(serve.SEED + 3, 40, 300.0)
+    outs = {}
+
+    def keep(r, executor):
+        outs[r.rid] = (r, executor.output(r).cpu())
+
+    lib.apply_tune_db()
+    try:
+        st = serve.Engine(ex, ex.budget(), streams=3).run(trace, on_complete=keep)
+    finally:
+        for op in (lib.OP_NTT_FWD, lib.OP_NTT_INV, lib.OP_POLYMUL):
+            for n in range(1, 18):
+                lib.pm_tune_set(op, n, 0)
+                lib.pm_tune_set_small(op, n, 0, 0)
+                lib.pm_tune_set_small_limit(op, n, 0)
+        lib.pm_tune_set_small_batch(0)
+    # 40 requests in B batches leave at least 2B - 40 batches of one request
+    assert st["completed"] == 40 and st["batches"] >= 24, st
+    for rid, (r, mix) in sorted(outs.items()):
+        alone = ex.run_alone(r).cpu()
+        assert np.array_equal(alone.numpy(), mix.numpy()), "request %d: single-request path vs jobs path" % rid
