@@ -16,6 +16,7 @@ Operands: uniform in [0, q) from the seeded device generator. Every timing is
 the median of HIP-event intervals between consecutive calls on one stream.
 
 Usage on a GPU:  python -m paper_2209_01290_amd.scaling [--max-log2p 15] [--out F]
+                 [--single [--log2n 10-17]]   (single transforms only)
 """
 from __future__ import annotations
 
@@ -98,11 +99,11 @@ def batch_scaling(torch, lib, log2n=16, max_log2p=15, verbose=True):
     return rows
 
 
-def single_scaling(torch, lib, verbose=True):
+def single_scaling(torch, lib, verbose=True, log2ns=range(10, 18)):
     from . import synth
     dev = torch.device("cuda")
     rows = []
-    for log2n in range(10, 18):
+    for log2n in log2ns:
         N = 1 << log2n
         prm = lib.Params(N, 1, device=dev)
         a, _ = synth.operands(SEED, prm.q, 1, N)
@@ -136,13 +137,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--max-log2p", type=int, default=15)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--single", action="store_true", help="only the single-transform scaling")
+    ap.add_argument("--log2n", default="10-17", help="range lo-hi of log2 N for the single transforms")
     a = ap.parse_args()
     import torch
     from . import lib
     lib.load()
     lib.apply_tune_db()
-    single = single_scaling(torch, lib)
-    batch = batch_scaling(torch, lib, max_log2p=a.max_log2p)
+    lo, hi = (int(v) for v in a.log2n.split("-"))
+    single = single_scaling(torch, lib, log2ns=range(lo, hi + 1))
+    batch = [] if a.single else batch_scaling(torch, lib, max_log2p=a.max_log2p)
     print(markdown(batch, single), flush=True)
     if a.out:
         with open(a.out, "w") as f:
