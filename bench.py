@@ -404,6 +404,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the batched step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time only plain device copies of 1 GiB (calibrates HBM byte counters)")
+    ap.add_argument("--words32-only", action="store_true",
+                    help="run only the 32-bit word measurement (for counter runs on its kernels)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the workload's limbs are independent and would be "
@@ -419,6 +421,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_probe:
         copy_probe(torch, dev, args.steps)
+        return
+    if args.words32_only:
+        print(json.dumps({"words32": words32(torch, lib, dev, steps=args.steps)}), flush=True)
         return
     N = 1 << N_LOG2
     prm = lib.Params(N, LIMBS, device=dev)
