@@ -151,7 +151,8 @@ def _calls(lib, name, prm, N, polys, da, db, dc, x, ws):
 
 
 LIMIT_MIN_LOG2N = 8            # per-N limits for N >= 2^8; the global threshold below
-LIMIT_MAX_WORDS = 1 << 22      # largest batch the limit search tries (32 MiB per operand)
+LIMIT_MAX_WORDS = 1 << 24      # largest batch the limit search tries (128 MiB per operand)
+UNLIMITED = (1 << 64) - 1      # limit recorded when the small plan still wins at LIMIT_MAX_WORDS
 
 
 def tune_small(log2ns, device="cuda", verbose=True):
@@ -192,7 +193,9 @@ def tune_small(log2ns, device="cuda", verbose=True):
                                                                     lat[name][str(log2n)]), flush=True)
     # Per-(op, N) limit: the largest batch (polynomials doubled from 1, up to
     # LIMIT_MAX_WORDS words) at which the small plan still beats the
-    # throughput plan; the search stops after two sizes in a row lost.
+    # throughput plan; the search stops after two sizes in a row lost. A plan
+    # that still wins at the largest size (the GPU long full, the time per
+    # polynomial steady) has no limit.
     cross = {}
     limits = {k: {} for k in OPS}
     for log2n in log2ns:
@@ -200,7 +203,7 @@ def tune_small(log2ns, device="cuda", verbose=True):
             continue
         N = 1 << log2n
         prm = lib.Params(N, 1, device=dev)
-        pmax = LIMIT_MAX_WORDS // N
+        pmax = min(LIMIT_MAX_WORDS // N, 1 << 15)       # at most 65535 polynomials per call
         a, b = synth.operands(synth.SEED_BASE + 19, prm.q, pmax, N)
         da_all, db_all = lib.to_device(a, dev), lib.to_device(b, dev)
         for name, op in OPS.items():
@@ -223,12 +226,15 @@ def tune_small(log2ns, device="cuda", verbose=True):
                 else:
                     lost += 1
                 polys *= 2
+            if won == N * pmax:
+                won = UNLIMITED
             limits[name][str(log2n)] = won
             lib.pm_tune_set_small_limit(op, log2n, won)
             if verbose:
                 print("[tune-small] limit %-8s N=2^%-2d: small plan up to %d words" % (name, log2n, won), flush=True)
     # the global threshold (for N without a limit): the smallest limit
     max_words = min((w for t in limits.values() for w in t.values()), default=0)
+    max_words = min(max_words, LIMIT_MAX_WORDS)
     lib.pm_tune_set_small_batch(max_words)
     return {"max_words": max_words, "choices": choices, "limits": limits, "latency_us": lat,
             "crossover_us": cross}
