@@ -354,12 +354,14 @@ def single_polymul(torch, lib, dev):
     da, db = lib.to_device(a, dev), lib.to_device(b, dev)
     dc = torch.empty_like(da)
     fn = lambda: lib.pm_polymul(da, db, dc, N, 1, 1, prm.q, prm.psi_br, prm.psi_inv_br, None)
-    out = {"what": "one N=1024 product, q = 2^60 - 2^14 + 1", "small_plan": lib.pm_tune_get_small(lib.OP_POLYMUL, 10),
+    plan = lib.pm_tune_get_small(lib.OP_POLYMUL, 10)
+    out = {"what": "one N=1024 product, q = 2^60 - 2^14 + 1", "small_plan": plan,
            "device_us": round(_graph_call_us(torch, fn), 2)}
-    keep = lib.pm_tune_get_small_batch()
-    lib.pm_tune_set_small_batch(0)
+    # the throughput plan: the small-batch plan of (polymul, 2^10) removed for one measurement
+    lib.pm_tune_set_small(lib.OP_POLYMUL, 10, 0, 0)
     out["device_us_throughput_plan"] = round(_graph_call_us(torch, fn), 2)
-    lib.pm_tune_set_small_batch(keep)
+    if plan[0]:
+        lib.pm_tune_set_small(lib.OP_POLYMUL, 10, *plan)
     out["host_call_us"] = round(_median_call_us(torch, torch.cuda.current_stream(dev), fn, 200), 2)
     return out
 

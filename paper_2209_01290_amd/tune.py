@@ -64,6 +64,10 @@ def tune(log2ns, words=1 << 25, device="cuda", verbose=True):
     from . import lib, synth
     lib.load()
     dev = torch.device(device)
+    # time the throughput plans only: no small-batch plan may take a call
+    for op in OPS.values():
+        for n in range(1, 18):
+            lib.pm_tune_set_small(op, n, 0, 0)
     choices = {k: {} for k in OPS}
     timings = {k: {} for k in OPS}
     for log2n in log2ns:
