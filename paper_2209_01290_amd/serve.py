@@ -394,13 +394,15 @@ def warm_up(ex):
         ex.run_alone(Request(i, 0.0, log2n, 2))
 
 
-def run_rates(rates, nreq, budget_gib=32.0, streams=3, seed=SEED, verbose=True, ex=None):
-    ex = ex or GpuExecutor(int(budget_gib * (1 << 30)), streams=streams, seed=seed)
+def run_rates(rates, nreq, budget_gib=32.0, streams=3, seed=SEED, verbose=True, ex=None,
+              max_batch_products=4096, ws_gib=2.0):
+    ex = ex or GpuExecutor(int(budget_gib * (1 << 30)), streams=streams, seed=seed,
+                           ws_bytes_per_stream=int(ws_gib * (1 << 30)))
     warm_up(ex)
     out = []
     for rate in rates:
         trace = [(t, n, L) for (t, n, L) in workloads.serving_requests(seed + int(rate), nreq, rate)]
-        eng = Engine(ex, ex.budget(), streams=streams)
+        eng = Engine(ex, ex.budget(), streams=streams, max_batch_products=max_batch_products)
         st = eng.run(trace)
         st.pop("_requests")
         st["offered_rate_req_s"] = rate
@@ -416,11 +418,14 @@ def main():
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--streams", type=int, default=3)
+    ap.add_argument("--max-batch-products", type=int, default=4096, help="limb-products per batch at most")
+    ap.add_argument("--ws-gib", type=float, default=2.0, help="batch workspace per stream (GiB)")
     a = ap.parse_args()
     from . import lib
     lib.load()
     lib.apply_tune_db()
-    run_rates([float(x) for x in a.rates.split(",")], a.requests, a.budget_gib, a.streams)
+    run_rates([float(x) for x in a.rates.split(",")], a.requests, a.budget_gib, a.streams,
+              max_batch_products=a.max_batch_products, ws_gib=a.ws_gib)
 
 
 if __name__ == "__main__":
