@@ -67,3 +67,25 @@ def first_mismatch(got, want):
     i = int(bad[0])
     return "%d mismatches, first at flat index %d: got %d want %d" % (
         bad.size, i, int(got.reshape(-1)[i]), int(want.reshape(-1)[i]))
+
+
+class tuned:
+    """Context manager: the packaged tuning database installed (the plans
+    bench.py runs), every plan table back to the library defaults on exit."""
+
+    def __init__(self, L):
+        self.L = L
+
+    def __enter__(self):
+        self.L.apply_tune_db()
+        return self
+
+    def __exit__(self, *exc):
+        L = self.L
+        for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
+            for n in range(1, 18):
+                L.pm_tune_set(op, n, 0)
+                L.pm_tune_set_small(op, n, 0, 0)
+                L.pm_tune_set_small_limit(op, n, 0)
+        L.pm_tune_set_small_batch(0)
+        return False

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import first_mismatch
+from gpu_helpers import first_mismatch, tuned
 from paper_2209_01290_amd import synth, workloads
 
 pytestmark = pytest.mark.gpu
@@ -37,7 +37,8 @@ def test_config4_mixed_full_size(L):
     reqs = workloads.mixed_requests(synth.SEED_BASE + 4)
     assert len(reqs) == 512 and {n for n, _ in reqs} == set(range(12, 18))
     mb = workloads.MixedBatch(reqs, synth.SEED_BASE + 4, torch.device("cuda"))
-    plan = L.pm_plan_create(mb.jobs)
+    with tuned(L):                       # plans read the tuned table at creation, as in the benchmark
+        plan = L.pm_plan_create(mb.jobs)
     try:
         L.pm_plan_launch(plan)
         torch.cuda.synchronize()

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import first_mismatch
+from gpu_helpers import first_mismatch, tuned
 from paper_2209_01290_amd import serve, synth, workloads
 
 pytestmark = pytest.mark.gpu
@@ -71,16 +71,8 @@ def test_single_request_batches_match_jobs_path(ex):
     def keep(r, executor):
         outs[r.rid] = (r, executor.output(r).cpu())
 
-    lib.apply_tune_db()
-    try:
+    with tuned(lib):
         st = serve.Engine(ex, ex.budget(), streams=3).run(trace, on_complete=keep)
-    finally:
-        for op in (lib.OP_NTT_FWD, lib.OP_NTT_INV, lib.OP_POLYMUL):
-            for n in range(1, 18):
-                lib.pm_tune_set(op, n, 0)
-                lib.pm_tune_set_small(op, n, 0, 0)
-                lib.pm_tune_set_small_limit(op, n, 0)
-        lib.pm_tune_set_small_batch(0)
     # 40 requests in B batches leave at least 2B - 40 batches of one request
     assert st["completed"] == 40 and st["batches"] >= 24, st
     for rid, (r, mix) in sorted(outs.items()):

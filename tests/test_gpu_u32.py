@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import first_mismatch, operands, oracle_ntt_fwd, oracle_ntt_inv, oracle_polymul, oracle_tables
+from gpu_helpers import first_mismatch, operands, oracle_ntt_fwd, oracle_ntt_inv, oracle_polymul, oracle_tables, tuned
 
 pytestmark = pytest.mark.gpu
 
@@ -234,8 +234,7 @@ def test_words32_full_size(L):
     oracle on sampled polynomials (a limb of each launch) and coefficients."""
     import torch
     N, limbs, polys = 1 << 16, 96, 8
-    L.apply_tune_db()
-    try:
+    with tuned(L):
         prm = L.Params32(N, limbs, bits=30)
         qs = prm.q
         a, b = operands(N, qs, polys, request=2000)
@@ -252,9 +251,3 @@ def test_words32_full_size(L):
         for _ in range(8):
             l, p, k = int(rng.integers(limbs)), int(rng.integers(polys)), int(rng.integers(N))
             assert int(got[l, p, k]) == o.polymul_coeff(a[l, p], b[l, p], qs[l], k), (l, p, k)
-    finally:
-        for op in (L.OP_NTT_FWD, L.OP_NTT_INV, L.OP_POLYMUL):
-            for n in range(1, 18):
-                L.pm_tune_set(op, n, 0)
-                L.pm_tune_set_small(op, n, 0, 0)
-        L.pm_tune_set_small_batch(0)
