@@ -40,12 +40,26 @@ SEED = 220901290 + 3
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one 32-bit VALU lane-op per
 # lane per cycle; HBM3E peak 8 TB/s.
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+CLOCK_MHZ = 2400.0
+PEAK_VALU_TOPS = 256 * 4 * 16 * CLOCK_MHZ * 1e6 / 1e12
 PEAK_HBM_GBPS = 8000.0
 # VALU instructions per unit of the method's work, counted in the ISA of
 # register-resident loops over the device arithmetic (modarith.hpp).
-OPS_CT, OPS_GS, OPS_MUL = 34, 46, 24
+OPS_CT, OPS_GS, OPS_MUL = 32, 44, 22
 
+
+# The same counts by instruction class: each class is priced by the probe
+# instruction that stands for it (pm_probe_valu's measured issue rates), which
+# gives the VALU-bound time of a launch for this instruction mix.
+MIX = {
+    "ct": {"v_mad_u64_u32": 8, "v_mul_hi_u32": 1, "v_mul_lo_u32": 2, "v_add3_u32": 1, "v_alignbit_b32": 2,
+           "v_lshl_add_u64": 2, "v_sub_co_u32": 15, "v_mov_b32": 1},
+    "gs": {"v_mad_u64_u32": 8, "v_mul_hi_u32": 1, "v_mul_lo_u32": 2, "v_add3_u32": 3, "v_alignbit_b32": 2,
+           "v_lshl_add_u64": 6, "v_sub_co_u32": 15, "v_xor_b32": 6, "v_mov_b32": 1},
+    "mul": {"v_mad_u64_u32": 8, "v_mul_hi_u32": 1, "v_mul_lo_u32": 2, "v_add3_u32": 1, "v_alignbit_b32": 2,
+            "v_sub_co_u32": 7, "v_mov_b32": 1},
+}
+assert (sum(MIX["ct"].values()), sum(MIX["gs"].values()), sum(MIX["mul"].values())) == (OPS_CT, OPS_GS, OPS_MUL)
 
 # The same counts for 32-bit words (modarith32.hpp), moduli with m <= 29 /
 # m = 30 (one more shift per modular product).
@@ -77,6 +91,14 @@ def alg_ops(name: str, N: int, limbs: int, polys: int, ops=(OPS_CT, OPS_GS, OPS_
         per = (R // 2) * int(logr) * (ct if mode == "fwd" else gs)
         return float(cols * nops * per)
     return float("nan")
+
+
+def mix_ceiling(name: str, N: int, limbs: int, polys: int, rates: dict) -> float:
+    """T lane-ops/s a launch of `name` could reach if the VALU issued every
+    instruction of its mix at the rate pm_probe_valu measured for its class."""
+    secs = alg_ops(name, N, limbs, polys,
+                   ops=tuple(sum(n / rates[i] for i, n in MIX[u].items()) for u in ("ct", "gs", "mul")))
+    return alg_ops(name, N, limbs, polys) / secs / 1e12
 
 
 # The sources the reported row kernel is compiled from: the counter summary
@@ -343,6 +365,19 @@ def words32(torch, lib, dev, steps=20):
                              "ops_per_unit": {"ct": OPS32[30][0], "gs": OPS32[30][1], "mul": OPS32[30][2]}}}}
 
 
+def valu_issue(lib):
+    """Lane-operations per second of each VALU instruction class the
+    butterflies use (pm_probe_valu: 32 independent chains per thread, every CU
+    busy) and the shader clock under that load."""
+    rates, mhz = lib.pm_probe_valu()
+    return {"clock_mhz_under_load": round(mhz, 1),
+            "lane_ops_T": {k: round(v / 1e12, 2) for k, v in rates.items()},
+            "peak_T_at_2400MHz_one_instruction_per_lane_per_cycle": round(PEAK_VALU_TOPS, 2),
+            "what": "multiplies, v_mad_u64_u32, three-operand and carry arithmetic issue at one "
+                    "instruction per lane per cycle (16 lanes per SIMD); two-operand moves and "
+                    "some logic issue faster"}
+
+
 def single_polymul(torch, lib, dev):
     """The latency-bound case: one product at N = 1024 under q = 2^60 - 2^14 + 1
     (the largest 60-bit prime = 1 mod 2048), device time per call from HIP-graph
@@ -406,6 +441,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the batched step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time only plain device copies of 1 GiB (calibrates HBM byte counters)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only measure the VALU issue rates and the shader clock under load")
     ap.add_argument("--words32-only", action="store_true",
                     help="run only the 32-bit word measurement (for counter runs on its kernels)")
     args = ap.parse_args()
@@ -426,6 +463,9 @@ def main():
         return
     if args.words32_only:
         print(json.dumps({"words32": words32(torch, lib, dev, steps=args.steps)}), flush=True)
+        return
+    if args.valu_probe:
+        print(json.dumps({"valu_issue": valu_issue(lib)}), flush=True)
         return
     N = 1 << N_LOG2
     prm = lib.Params(N, LIMBS, device=dev)
@@ -483,6 +523,12 @@ def main():
                 "traffic": measured_traffic(dom), "kernel": dom,
                 "kernel_avg_ms": round(dom_avg_s * 1e3, 4),
                 "alg_ops_per_launch": ops}
+    # the issue ceiling measured live (after the timed regions): the rates of
+    # the butterflies' instruction classes and the shader clock under load
+    issue = valu_issue(lib)
+    ceiling = mix_ceiling(dom, N, LIMBS, POLYS, {k: v * 1e12 for k, v in issue["lane_ops_T"].items()})
+    roofline["peak_mix_measured"] = round(ceiling, 3)
+    roofline["frac_of_mix_measured"] = round(achieved / ceiling, 4)
     # HBM view of the whole step: operands and result once, tables once per limb
     b_alg = products * 24 * N + LIMBS * 16 * N
     hbm = {"alg_bytes_per_step": b_alg,
@@ -504,6 +550,7 @@ def main():
         "latency_ms": {"p50": round(pct(step_ms, 50), 4), "p99": round(pct(step_ms, 99), 4),
                        "unit": "per batched step of 384 products"},
         "roofline": roofline,
+        "valu_issue": issue,
         "hbm_roofline": hbm,
         "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(kern.items())},
         "kernel_timing": {"steps": args.steps, "ms_per_step_with_kernel_timer": round(timed_step_ms, 4)},

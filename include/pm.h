@@ -290,6 +290,23 @@ typedef struct {
 int pm_prof_enable(int on);
 int pm_prof_read(pm_prof_entry *out, size_t cap, size_t *n, int reset);
 
+/* ------------------------------------------------------ VALU issue-rate probe
+ * A measurement helper, not part of the method: the lane-operations per
+ * second the device issues for each class of VALU instruction the butterflies
+ * are built from (v_mad_u64_u32, 32-bit multiplies, three-operand and carry
+ * arithmetic, 64-bit shifted add, two-operand add / xor, move), each measured
+ * with 32 independent register chains per thread and every CU busy, and the
+ * shader clock under that load (*clock_mhz; core-clock counter against the
+ * 100 MHz real-time counter). out (host, cap entries) receives one entry per
+ * instruction, *n their number. Synchronous on the current device: allocates
+ * a device buffer of 16 x 256 x 8 bytes per CU and frees it before returning.
+ */
+typedef struct {
+  char name[24];
+  double lane_ops_per_s;
+} pm_probe_entry;
+int pm_probe_valu(pm_probe_entry *out, size_t cap, size_t *n, double *clock_mhz);
+
 /* ---------------------------------------------------------------- host helpers
  * Parameter generation on the host (no device work).
  *

@@ -119,12 +119,14 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Mod& M)
     quot >>= M.t;
   }
 
-  // r = x - quot*q  (mod 2^64), then at most one correctional subtraction
+  // r = x - quot*q  (mod 2^64), then at most one correctional subtraction.
+  // The cross products of quot*(2^64 - q) only reach the high word: they are
+  // summed in 32 bits and added to it directly.
   const uint64_t nq = 0 - M.q;
   const uint32_t k0 = lo32(quot), k1 = hi32(quot);
-  uint64_t r = (uint64_t)k0 * lo32(nq) + (((uint64_t)x1 << 32) | x0);
-  r += (uint64_t)(k0 * hi32(nq) + k1 * lo32(nq)) << 32;
-  return csub(r, M.q);
+  const uint64_t r0 = (uint64_t)k0 * lo32(nq) + (((uint64_t)x1 << 32) | x0);
+  const uint32_t cross = lo32((uint64_t)k1 * lo32(nq) + (uint32_t)(k0 * hi32(nq)));
+  return csub(pack64(lo32(r0), hi32(r0) + cross), M.q);
 }
 
 // CT butterfly of the merged forward NTT (Alg. 5):

@@ -1,0 +1,160 @@
+// VALU issue-rate probe (a measurement helper behind pm_probe_valu, not part
+// of the method): how many lane-operations per second the GPU issues for each
+// class of VALU instruction the butterflies are built from, and the shader
+// clock under that load. Each thread runs 32 independent register chains of
+// one instruction (inline assembly, so nothing is folded or reordered away),
+// 16 workgroups of 256 threads per CU; the best of three timed launches is
+// kept. The clock is the core-clock counter (s_memtime) against the 100 MHz
+// real-time counter (s_memrealtime) across a busy loop.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/pm.h"
+#include "pm_host.hpp"
+
+namespace pm {
+namespace {
+
+constexpr int PROBE_CH = 32;
+constexpr int PROBE_WG = 256;
+
+enum { P_MAD64, P_MULHI, P_MULLO, P_ALIGNBIT, P_ADD3, P_SUBCO, P_LSHLADD64, P_ADD, P_XOR, P_MOV, P_COUNT };
+const char* const PROBE_NAMES[P_COUNT] = {"v_mad_u64_u32", "v_mul_hi_u32", "v_mul_lo_u32", "v_alignbit_b32",
+                                          "v_add3_u32",    "v_sub_co_u32", "v_lshl_add_u64", "v_add_u32",
+                                          "v_xor_b32",     "v_mov_b32"};
+
+// out: one word per thread (gridDim.x * PROBE_WG words).
+template <int OP>
+__global__ void __launch_bounds__(PROBE_WG) k_probe(uint64_t* out, int iters, uint32_t s) {
+  uint32_t a[PROBE_CH];
+  uint64_t w[PROBE_CH];
+  const uint32_t x = threadIdx.x * 7u + s, y = threadIdx.x ^ s;
+  for (int i = 0; i < PROBE_CH; ++i) {
+    a[i] = y + i;
+    w[i] = ((uint64_t)x << 32) | (y + i);
+  }
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < PROBE_CH; ++i) {
+      uint64_t sd;
+      if (OP == P_MAD64) asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(w[i]), "=s"(sd) : "v"(x), "v"(y));
+      if (OP == P_MULHI) asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(a[i]) : "v"(x));
+      if (OP == P_MULLO) asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(a[i]) : "v"(x));
+      if (OP == P_ALIGNBIT) asm volatile("v_alignbit_b32 %0, %0, %1, 7" : "+v"(a[i]) : "v"(x));
+      if (OP == P_ADD3) asm volatile("v_add3_u32 %0, %0, %1, %2" : "+v"(a[i]) : "v"(x), "v"(y));
+      if (OP == P_SUBCO) asm volatile("v_sub_co_u32 %0, %1, %0, %2" : "+v"(a[i]), "=s"(sd) : "v"(x));
+      if (OP == P_LSHLADD64) asm volatile("v_lshl_add_u64 %0, %0, 0, %1" : "+v"(w[i]) : "v"(w[(i + 1) % PROBE_CH]));
+      if (OP == P_ADD) asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[i]) : "v"(x));
+      if (OP == P_XOR) asm volatile("v_xor_b32 %0, %0, %1" : "+v"(a[i]) : "v"(x));
+      if (OP == P_MOV) asm volatile("v_mov_b32 %0, %1" : "=v"(a[i]) : "v"(a[(i + 1) % PROBE_CH]));
+    }
+  }
+  uint64_t r = 0;
+  for (int i = 0; i < PROBE_CH; ++i) r ^= a[i] ^ w[i];
+  out[(size_t)blockIdx.x * PROBE_WG + threadIdx.x] = r;
+}
+
+// out: two words per workgroup (core-clock ticks, real-time ticks).
+__global__ void __launch_bounds__(PROBE_WG) k_clock(uint64_t* out, int iters, uint32_t s) {
+  const uint64_t t0 = __builtin_amdgcn_s_memtime(), r0 = __builtin_amdgcn_s_memrealtime();
+  uint32_t a[8];
+  for (int i = 0; i < 8; ++i) a[i] = threadIdx.x + i + s;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) asm volatile("v_add3_u32 %0, %0, %1, %1" : "+v"(a[i]) : "v"(s));
+  }
+  const uint64_t t1 = __builtin_amdgcn_s_memtime(), r1 = __builtin_amdgcn_s_memrealtime();
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = t1 - t0;
+    out[2 * blockIdx.x + 1] = r1 - r0;
+  }
+}
+
+template <int OP>
+hipError_t launch_probe(uint64_t* out, int blocks, int iters, hipStream_t s) {
+  hipLaunchKernelGGL((k_probe<OP>), dim3(blocks), dim3(PROBE_WG), 0, s, out, iters, 12345u);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_op(int op, uint64_t* out, int blocks, int iters, hipStream_t s) {
+  switch (op) {
+    case P_MAD64: return launch_probe<P_MAD64>(out, blocks, iters, s);
+    case P_MULHI: return launch_probe<P_MULHI>(out, blocks, iters, s);
+    case P_MULLO: return launch_probe<P_MULLO>(out, blocks, iters, s);
+    case P_ALIGNBIT: return launch_probe<P_ALIGNBIT>(out, blocks, iters, s);
+    case P_ADD3: return launch_probe<P_ADD3>(out, blocks, iters, s);
+    case P_SUBCO: return launch_probe<P_SUBCO>(out, blocks, iters, s);
+    case P_LSHLADD64: return launch_probe<P_LSHLADD64>(out, blocks, iters, s);
+    case P_ADD: return launch_probe<P_ADD>(out, blocks, iters, s);
+    case P_XOR: return launch_probe<P_XOR>(out, blocks, iters, s);
+    case P_MOV: return launch_probe<P_MOV>(out, blocks, iters, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+}  // namespace pm
+
+using namespace pm;
+
+extern "C" int pm_probe_valu(pm_probe_entry* out, size_t cap, size_t* n, double* clock_mhz) {
+  if (!out || !n || !clock_mhz) return set_error(PM_EINVAL, "pm_probe_valu: null argument");
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess || cus <= 0) return set_error(PM_EHIP, "pm_probe_valu: no HIP device");
+  const int blocks = 16 * cus, iters = 512;
+  uint64_t* buf = nullptr;
+  if (hipMalloc((void**)&buf, (size_t)blocks * PROBE_WG * sizeof(uint64_t)) != hipSuccess)
+    return set_error(PM_ENOMEM, "pm_probe_valu: device buffer");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t s = nullptr;
+  int rc = PM_OK;
+  if (hipStreamCreate(&s) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = set_error(PM_EHIP, "pm_probe_valu: stream or events");
+  *n = 0;
+  for (int op = 0; rc == PM_OK && op < P_COUNT; ++op) {
+    float best = 0.f;
+    for (int rep = 0; rep < 4 && rc == PM_OK; ++rep) {
+      float ms = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess || launch_probe_op(op, buf, blocks, iters, s) != hipSuccess ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = set_error(PM_EHIP, "pm_probe_valu: probe launch");
+        break;
+      }
+      if (rep > 0 && (best == 0.f || ms < best)) best = ms;   // the first launch loads the code
+    }
+    if (rc == PM_OK && (size_t)op < cap) {
+      strncpy(out[op].name, PROBE_NAMES[op], sizeof(out[op].name) - 1);
+      out[op].name[sizeof(out[op].name) - 1] = 0;
+      out[op].lane_ops_per_s = (double)blocks * PROBE_WG * iters * PROBE_CH / (best * 1e-3);
+      *n = (size_t)op + 1;
+    }
+  }
+  if (rc == PM_OK) {
+    hipLaunchKernelGGL(k_clock, dim3(blocks), dim3(PROBE_WG), 0, s, buf, 8192, 7u);
+    std::vector<uint64_t> h(2 * (size_t)blocks);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(h.data(), buf, h.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess) {
+      rc = set_error(PM_EHIP, "pm_probe_valu: clock probe");
+    } else {
+      double sum = 0;
+      int cnt = 0;
+      for (int b = 0; b < blocks; ++b)
+        if (h[2 * b + 1]) {
+          sum += (double)h[2 * b] / (double)h[2 * b + 1];
+          ++cnt;
+        }
+      *clock_mhz = cnt ? 100.0 * sum / cnt : 0.0;
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (s) hipStreamDestroy(s);
+  hipFree(buf);
+  return rc;
+}

@@ -27,6 +27,10 @@ _lock = threading.Lock()
 _lib = None
 
 
+class ProbeEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("lane_ops_per_s", ctypes.c_double)]
+
+
 class ProfEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
@@ -89,6 +93,8 @@ def load():
             "pm_reduce_apply": (i32, [i32, ctypes.c_uint, vp, vp, vp, vp, sz, u64, vp]),
             "pm_reduce_chain": (i32, [i32, ctypes.c_uint, vp, sz, u64, i32, u64, vp]),
             "pm_prof_read": (i32, [ctypes.POINTER(ProfEntry), sz, ctypes.POINTER(sz), i32]),
+            "pm_probe_valu": (i32, [ctypes.POINTER(ProbeEntry), sz, ctypes.POINTER(sz),
+                                    ctypes.POINTER(ctypes.c_double)]),
             "pm_ntt_fwd_il": (i32, [vp, sz, sz, sz, u64p, vp, vp]),
             "pm_ntt_inv_il": (i32, [vp, sz, sz, sz, u64p, vp, vp]),
             "pm_polymul_il": (i32, [vp, vp, vp, sz, sz, sz, u64p, vp, vp, vp, vp]),
@@ -113,7 +119,7 @@ def exported_symbols():
     return ["pm_last_error", "pm_barrett_mulmod", "pm_ntt_fwd", "pm_ntt_inv", "pm_polymul", "pm_polymul_fused",
             "pm_polymul_workspace_bytes", "pm_polymul_stagewise",
             "pm_polymul_stagewise_workspace_bytes", "pm_tune_set", "pm_tune_get",
-            "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read",
+            "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read", "pm_probe_valu",
             "pm_polymul_jobs_workspace_bytes", "pm_polymul_jobs", "pm_plan_create", "pm_plan_launch",
             "pm_plan_destroy", "pm_plan_device_bytes", "pm_reduce_apply", "pm_reduce_chain",
             "pm_ntt_fwd_u32", "pm_ntt_inv_u32", "pm_polymul_u32", "pm_polymul_fused_u32",
@@ -451,6 +457,17 @@ def pm_prof_read(reset=True):
     _check(lib.pm_prof_read(buf, cap, ctypes.byref(n), 1 if reset else 0), "pm_prof_read")
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
             for i in range(min(n.value, cap))}
+
+
+def pm_probe_valu():
+    """({instruction: lane-ops/s}, shader clock MHz under load) on the current device."""
+    lib = load()
+    cap = 16
+    buf = (ProbeEntry * cap)()
+    n = ctypes.c_size_t(0)
+    mhz = ctypes.c_double(0)
+    _check(lib.pm_probe_valu(buf, cap, ctypes.byref(n), ctypes.byref(mhz)), "pm_probe_valu")
+    return {buf[i].name.decode(): float(buf[i].lane_ops_per_s) for i in range(min(n.value, cap))}, mhz.value
 
 
 def pm_ntt_primes(N, count, bits=60):
