@@ -150,6 +150,21 @@ __device__ __forceinline__ void gs_bfly_half(uint64_t& u, uint64_t& v, uint64_t 
   v = mulmod<KIND>(halfmod(d, M.half), xi, M);
 }
 
+// xi/2 mod q, for gs_bfly_htw.
+__device__ __forceinline__ uint64_t half_tw(uint64_t xi, const Mod& M) { return halfmod(xi, M.half); }
+
+// gs_bfly_half with the twiddle halved beforehand (xh = xi/2 mod q):
+// (u, v) -> ((u+v)/2, (u-v) xh); in Z_q, (u-v) xh = xi (u-v)/2. Where one
+// twiddle serves several butterflies, its halving is paid once instead of
+// once per butterfly.
+template <int KIND>
+__device__ __forceinline__ void gs_bfly_htw(uint64_t& u, uint64_t& v, uint64_t xh, const Mod& M) {
+  const uint64_t s = addmod(u, v, M.q);
+  const uint64_t d = submod(u, v, M.q);
+  u = halfmod(s, M.half);
+  v = mulmod<KIND>(d, xh, M);
+}
+
 // Unhalved GS butterfly (Alg. 6 as printed): (u, v) -> (u+v, xi*(u-v)).
 template <int KIND>
 __device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, uint64_t xi, const Mod& M) {

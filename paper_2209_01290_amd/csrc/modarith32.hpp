@@ -64,4 +64,17 @@ __device__ __forceinline__ void gs_bfly_half(uint32_t& u, uint32_t& v, uint32_t 
   v = mulmod<KIND>(halfmod(d, M.half), xi, M);
 }
 
+// xi/2 mod q, for gs_bfly_htw.
+__device__ __forceinline__ uint32_t half_tw(uint32_t xi, const Mod32& M) { return halfmod(xi, M.half); }
+
+// gs_bfly_half with the twiddle halved beforehand (xh = xi/2 mod q):
+// (u, v) -> ((u+v)/2, (u-v) xh); in Z_q, (u-v) xh = xi (u-v)/2.
+template <int KIND>
+__device__ __forceinline__ void gs_bfly_htw(uint32_t& u, uint32_t& v, uint32_t xh, const Mod32& M) {
+  const uint32_t s = addmod(u, v, M.q);
+  const uint32_t d = submod(u, v, M.q);
+  u = halfmod(s, M.half);
+  v = mulmod<KIND>(d, xh, M);
+}
+
 }  // namespace pm

@@ -148,11 +148,11 @@ __device__ __forceinline__ void inv_round(W (&x)[RowGeom<GEO>::E], uint32_t t, c
     const uint32_t base = Rr * mm + (th << (P + EB - b - 1));
 #pragma unroll
     for (int g = 0; g < (G::E >> (jb + 1)); ++g) {
-      const W xi = tw[base + g];
+      const W xh = half_tw(tw[base + g], M);     // halved once for its 2^jb butterflies
 #pragma unroll
       for (int s = 0; s < (1 << jb); ++s) {
         const int j = (g << (jb + 1)) | s;
-        gs_bfly_half<KIND>(x[j], x[j | (1 << jb)], xi, M);
+        gs_bfly_htw<KIND>(x[j], x[j | (1 << jb)], xh, M);
       }
     }
     stage_fence();
@@ -303,9 +303,9 @@ __device__ __forceinline__ void col_inv(W (&x)[1 << LOGR], const W* __restrict__
     const int m = 1 << lm, k = R >> (lm + 1);
 #pragma unroll
     for (int g = 0; g < m; ++g) {
-      const W xi = tw[m + g];
+      const W xh = half_tw(tw[m + g], M);
 #pragma unroll
-      for (int s = 0; s < k; ++s) gs_bfly_half<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xi, M);
+      for (int s = 0; s < k; ++s) gs_bfly_htw<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xh, M);
     }
   }
 }
@@ -340,9 +340,9 @@ __device__ __forceinline__ void blk_inv(W (&x)[1 << LOGR], const W* __restrict__
     const W* t = tw + (rb << lm);
 #pragma unroll
     for (int g = 0; g < m; ++g) {
-      const W xi = t[g];
+      const W xh = half_tw(t[g], M);
 #pragma unroll
-      for (int s = 0; s < k; ++s) gs_bfly_half<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xi, M);
+      for (int s = 0; s < k; ++s) gs_bfly_htw<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xh, M);
     }
   }
 }
