@@ -68,7 +68,7 @@ assert all(abs(sum(MIX[u].values()) - o) < 1e-9 for u, o in (("ct", OPS_CT), ("g
 
 # The same counts for 32-bit words (modarith32.hpp), moduli with m <= 29 /
 # m = 30 (one more shift per modular product).
-OPS32 = {29: (14, 21, 7), 30: (15, 22, 8)}
+OPS32 = {29: (14, 17 + 4 * TW_PER_GS, 7), 30: (15, 18 + 4 * TW_PER_GS, 8)}
 
 
 def alg_ops(name: str, N: int, limbs: int, polys: int, ops=(OPS_CT, OPS_GS, OPS_MUL)) -> float:
