@@ -1,0 +1,98 @@
+// Software-pipelined Eq. 2 (and the fused product of Alg. 8) over limb
+// chunks: the throughput plan with rows of 2^12 words after a column pass of
+// 2^3..2^5 rows (N = 2^15..2^17), 64-bit words.
+//
+// The column passes are bound by memory and the row pass by the VALU. With
+// the batch split into G chunks of limbs, launch j runs three independent
+// kinds of workgroup: the row pass of chunk j-1 (forward rows of a and b,
+// product, inverse rows), the forward column pass of chunk j and the inverse
+// column pass of chunk j-2. Their data are disjoint, and every dependency (a
+// chunk's rows after its forward columns, its inverse columns after its rows)
+// is between consecutive launches on one stream, so no workgroup ever waits
+// for another. The rows come first in each launch and the short column
+// workgroups after them, so the column work fills the CUs that the long row
+// workgroups leave idle as they finish. (Interleaving the kinds finely was
+// measured slower: row workgroups that start at scattered times next to
+// column workgroups lose the near-lockstep progress through their long,
+// fully unrolled code.) G + 2 launches per batch.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ntt_row.hpp"
+#include "pm_internal.hpp"
+#include "pm_pipe.hpp"
+
+namespace pm {
+namespace {
+
+constexpr int PIPE_LC = 12;                        // row length 2^12 (16 words per thread)
+using PG = RowGeom<PIPE_LC>;
+static_assert(PG::WG == 256 && PG::ROWS == 1, "one 2^12-word row per workgroup of 256 threads");
+constexpr uint32_t PIPE_CB = (1u << PIPE_LC) / 256;   // column blocks of 256 per polynomial
+
+// grid: nr row workgroups, then nf forward-column and ni inverse-column ones.
+template <int LOGR, int KIND, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_pipe(PipeArgs a, LimbSet ls) {
+  __shared__ uint64_t lds[PG::LDS_WORDS];
+  constexpr uint32_t R = 1u << LOGR;
+  const size_t N = (size_t)1 << (PIPE_LC + LOGR), C = (size_t)1 << PIPE_LC;
+  const uint32_t t = threadIdx.x, b = blockIdx.x;
+  if (b < a.nr) {
+    const uint32_t per_limb = a.polys * R;
+    const uint32_t limb = a.rl0 + b / per_limb, task = b % per_limb;
+    const size_t off = (size_t)limb * a.polys * N + ((size_t)task << PIPE_LC);
+    const Mod M = ls.mod[limb];
+    row_task<PIPE_LC, KIND, MODE>(a.C + off, a.WS + off, a.C + off, a.twf + (size_t)limb * N,
+                                  a.twi + (size_t)limb * N, R + (task & (R - 1)), true, M, lds, t);
+    return;
+  }
+  // column workgroups: forward (a -> C, b -> WS) or inverse (C in place)
+  const bool fwd = b < a.nr + a.nf;
+  const uint32_t idx = fwd ? b - a.nr : b - a.nr - a.nf;
+  const uint32_t nops = fwd ? 2u : 1u;
+  const uint32_t cb = idx % PIPE_CB;
+  uint32_t rest = idx / PIPE_CB;
+  const uint32_t op = rest % nops;
+  rest /= nops;
+  const uint32_t poly = rest % a.polys;
+  const uint32_t limb = (fwd ? a.fl0 : a.il0) + rest / a.polys;
+  const size_t off = ((size_t)limb * a.polys + poly) * N + (size_t)cb * 256 + t;
+  const uint64_t* src = fwd ? (op ? a.B : a.A) + off : a.C + off;
+  uint64_t* dst = fwd ? (op ? a.WS : a.C) + off : a.C + off;
+  const Mod M = ls.mod[limb];
+  uint64_t x[R];
+#pragma unroll
+  for (uint32_t i = 0; i < R; ++i) x[i] = src[i * C];
+  if (fwd) col_fwd<LOGR, KIND>(x, a.twf + (size_t)limb * N, M);
+  else col_inv<LOGR, KIND>(x, a.twi + (size_t)limb * N, M);
+#pragma unroll
+  for (uint32_t i = 0; i < R; ++i) dst[i * C] = x[i];
+}
+
+template <int LOGR, int MODE>
+void pipe_launch(const PipeArgs& a, const LimbSet& ls, int kind, hipStream_t s) {
+  const uint32_t blocks = a.nr + a.nf + a.ni;
+  if (kind == KIND_WIDE) hipLaunchKernelGGL((k_pipe<LOGR, KIND_WIDE, MODE>), dim3(blocks), dim3(256), 0, s, a, ls);
+  else hipLaunchKernelGGL((k_pipe<LOGR, KIND_ANY, MODE>), dim3(blocks), dim3(256), 0, s, a, ls);
+}
+
+template <int MODE>
+hipError_t pipe_launch_logr(int logr, const PipeArgs& a, const LimbSet& ls, int kind, hipStream_t s) {
+  switch (logr) {
+    case 3: pipe_launch<3, MODE>(a, ls, kind, s); break;
+    case 4: pipe_launch<4, MODE>(a, ls, kind, s); break;
+    case 5: pipe_launch<5, MODE>(a, ls, kind, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pipe(int logr, bool fused, const PipeArgs& a, const LimbSet& ls, int kind, hipStream_t s) {
+  if (a.nr + a.nf + a.ni == 0) return hipSuccess;
+  return fused ? pipe_launch_logr<ROW_FMUL>(logr, a, ls, kind, s) : pipe_launch_logr<ROW_MUL>(logr, a, ls, kind, s);
+}
+
+}  // namespace pm

@@ -14,6 +14,7 @@
 
 #include "../../include/pm.h"
 #include "pm_colq.hpp"
+#include "pm_pipe.hpp"
 #include "pm_host.hpp"
 #include "pm_internal.hpp"
 #include "pm_plan.hpp"
@@ -341,6 +342,18 @@ size_t polymul_workspace(size_t N, size_t limbs, size_t polys) {
   return p.R > 1 ? N * limbs * polys * sizeof(W) : 0;
 }
 
+// Chunks of the software-pipelined product for a launch group of nl limbs
+// and polys pairs per limb: 2 for batches of at least PIPE_MIN_PRODUCTS
+// products, else 0 (the three-pass form), unless pm_tune_set_pipeline chose.
+// At most nl chunks.
+constexpr size_t PIPE_MIN_PRODUCTS = 64;
+uint32_t pipe_chunks(size_t nl, size_t polys) {
+  const int set = plan_pipe();
+  size_t g = set >= 0 ? (size_t)set : (nl * polys >= PIPE_MIN_PRODUCTS ? 2 : 0);
+  if (g > nl) g = nl;
+  return g > 1 ? (uint32_t)g : 0u;
+}
+
 // Eq. 2 over a batch (fused: Alg. 8's rows instead of the pointwise rows).
 template <typename W>
 int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t polys, const W* q,
@@ -379,6 +392,28 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
       RowArgsT<W> ra{A + base, square ? nullptr : B + base, c + base, tf, ti, b.log2n, 1, (uint32_t)polys,
                      (uint32_t)nl, &ls};
       return run_row(p.logc, b.kind, mode, ra, s, ebx);
+    }
+    // software-pipelined form: G chunks of limbs, G + 2 launches (pipe_kernels.hip)
+    if constexpr (sizeof(W) == 8) {
+      uint32_t G = pipe_chunks(nl, polys);
+      if (G > 1 && !same && p.ebx == 4 && p.logc == 12 && p.logr >= 3 && p.logr <= 5) {
+        const uint32_t R = 1u << p.logr;
+        // a launch holds at most (R + 48) * polys * ceil(nl / G) workgroups;
+        // keep its grid under 2^32 threads
+        const size_t cap = (((size_t)1 << 24) - 1) / ((R + 48) * polys);
+        G = std::max<uint32_t>(G, (uint32_t)((nl + cap - 1) / cap));
+        auto lo = [&](uint32_t k) { return (uint32_t)(k * nl / G); };   // chunk k = limbs [lo(k), lo(k+1))
+        for (uint32_t j = 0; j < G + 2; ++j) {
+          PipeArgs pa{A + base, B + base, c + base, ws + base, tf, ti, (uint32_t)polys, 0, 0, 0, 0, 0, 0};
+          if (j >= 1 && j <= G) pa.rl0 = lo(j - 1), pa.nr = R * (uint32_t)polys * (lo(j) - lo(j - 1));
+          if (j < G) pa.fl0 = lo(j), pa.nf = 32u * (uint32_t)polys * (lo(j + 1) - lo(j));
+          if (j >= 2) pa.il0 = lo(j - 2), pa.ni = 16u * (uint32_t)polys * (lo(j - 1) - lo(j - 2));
+          ProfScope ps(s, fused ? "pipe_fmul_c12" : "pipe_mul_c12");
+          hipError_t e = launch_pipe((int)p.logr, fused, pa, ls, b.kind, s);
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+      }
     }
     // column stages of a (-> c) and b (-> workspace), fused rows, inverse columns of c
     W* wb = same ? c + base : ws + base;

@@ -16,6 +16,7 @@ std::atomic<uint32_t> g_small[OP_COUNT][PM_MAX_LOG2N + 1];
 std::atomic<size_t> g_small_words{0};
 // per (op, log2n) batch limit of the small-batch plan; 0 = g_small_words
 std::atomic<size_t> g_small_limit[OP_COUNT][PM_MAX_LOG2N + 1];
+std::atomic<int> g_pipe{-1};
 
 bool valid_split(unsigned log2n, unsigned logc) {
   if (logc > log2n || logc > PM_MAX_LOGC || log2n - logc > PM_MAX_LOGR) return false;
@@ -78,6 +79,9 @@ bool plan_small_limit_set(int op, unsigned log2n, size_t words) {
   g_small_limit[op][log2n].store(words);
   return true;
 }
+
+void plan_pipe_set(int chunks) { g_pipe.store(chunks < 0 ? -1 : chunks); }
+int plan_pipe() { return g_pipe.load(); }
 
 size_t plan_small_limit(int op, unsigned log2n) {
   if (op < 0 || op >= OP_COUNT || log2n < 1 || log2n > PM_MAX_LOG2N) return 0;
@@ -148,3 +152,10 @@ extern "C" int pm_tune_set_small_limit(int op, unsigned log2n, size_t max_words)
 }
 
 extern "C" size_t pm_tune_get_small_limit(int op, unsigned log2n) { return pm::plan_small_limit(op, log2n); }
+
+extern "C" int pm_tune_set_pipeline(int chunks) {
+  pm::plan_pipe_set(chunks);
+  return PM_OK;
+}
+
+extern "C" int pm_tune_get_pipeline(void) { return pm::plan_pipe(); }

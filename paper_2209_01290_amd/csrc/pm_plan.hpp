@@ -43,5 +43,9 @@ size_t plan_small_threshold();
 // threshold above); false for an invalid (op, log2n).
 bool plan_small_limit_set(int op, unsigned log2n, size_t words);
 size_t plan_small_limit(int op, unsigned log2n);
+// Limb chunks of the software-pipelined product: -1 = the built-in choice,
+// 0 or 1 = never pipelined, G >= 2 = G chunks (at most the launch group's limbs).
+void plan_pipe_set(int chunks);
+int plan_pipe();
 
 }  // namespace pm

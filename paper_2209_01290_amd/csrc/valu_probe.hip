@@ -152,9 +152,9 @@ extern "C" int pm_probe_valu(pm_probe_entry* out, size_t cap, size_t* n, double*
       *clock_mhz = cnt ? 100.0 * sum / cnt : 0.0;
     }
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  if (s) hipStreamDestroy(s);
-  hipFree(buf);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(buf);
   return rc;
 }

@@ -88,4 +88,5 @@ class tuned:
                 L.pm_tune_set_small(op, n, 0, 0)
                 L.pm_tune_set_small_limit(op, n, 0)
         L.pm_tune_set_small_batch(0)
+        L.pm_tune_set_pipeline(-1)
         return False
