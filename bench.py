@@ -6,8 +6,9 @@ q = 1 mod 2^17 (the 48 largest below 2^60), 8 independent polynomial pairs
 per limb, i.e. 384 products c = a (*) b in Z_q[x]/(x^65536 + 1), operands
 uniform in [0, q) from the seeded SplitMix64 generator. A step is one call of
 the batched entry point pm_polymul over the whole batch: forward merged CT
-NTT of a and b, pointwise product, halved merged GS inverse. Inputs, twiddle
-tables and outputs stay resident in HBM; the timed region holds only kernels.
+NTT of a and b, pointwise product, halved merged GS inverse (software-
+pipelined over two chunks of 24 limbs: 4 launches). Inputs, twiddle tables
+and outputs stay resident in HBM; the timed region holds only kernels.
 
 Reported beside the batched throughput:
   plain       the same 384 products as 384 separate pm_polymul calls (one
@@ -16,6 +17,8 @@ Reported beside the batched throughput:
   ntt_fwd     standalone forward transforms of the 384 a operands
   roofline    the dominant kernel's live average duration (HIP events on its
               own stream) against the VALU issue ceiling, with the HBM view
+  three_pass  the same step without pipelining (column, row, column pass)
+              and the row pass's own roofline
   cpu_baseline  the CPU oracle on a bounded sample of the same products
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
@@ -71,9 +74,12 @@ assert all(abs(sum(MIX[u].values()) - o) < 1e-9 for u, o in (("ct", OPS_CT), ("g
 OPS32 = {29: (14, 17 + 4 * TW_PER_GS, 7), 30: (15, 18 + 4 * TW_PER_GS, 8)}
 
 
-def alg_ops(name: str, N: int, limbs: int, polys: int, ops=(OPS_CT, OPS_GS, OPS_MUL)) -> float:
+def alg_ops(name: str, N: int, limbs: int, polys: int, ops=(OPS_CT, OPS_GS, OPS_MUL),
+            launches_per_step: int = 1) -> float:
     """Algorithmic VALU lane-ops one launch of kernel `name` performs
-    (row_* / row32_*: fused row pass; col_* / col32_*: column pass)."""
+    (row_* / row32_*: fused row pass; col_* / col32_*: column pass; pipe_*:
+    the software-pipelined product, whose launches_per_step launches share the
+    row and column work of one batch)."""
     ct, gs, mul = ops
     kind, _, rest = name.partition("_")
     if kind in ("row", "row32"):
@@ -85,8 +91,10 @@ def alg_ops(name: str, N: int, limbs: int, polys: int, ops=(OPS_CT, OPS_GS, OPS_
             per = 2 * half * ct + C * mul + half * gs
         elif mode == "fwd":
             per = half * ct
-        else:
+        elif mode == "inv":
             per = half * gs
+        else:
+            return float("nan")
         return float(rows * per)
     if kind in ("col", "col32"):
         mode, logr = rest.split("_r")
@@ -95,6 +103,14 @@ def alg_ops(name: str, N: int, limbs: int, polys: int, ops=(OPS_CT, OPS_GS, OPS_
         nops = 2 if mode == "fwd" else 1
         per = (R // 2) * int(logr) * (ct if mode == "fwd" else gs)
         return float(cols * nops * per)
+    if kind == "pipe":
+        mode, logc = rest.split("_c")
+        if mode != "mul":
+            return float("nan")
+        logr = N.bit_length() - 1 - int(logc)
+        step = sum(alg_ops(k, N, limbs, polys, ops) for k in
+                   ("row_mul_c%s" % logc, "col_fwd_r%d" % logr, "col_inv_r%d" % logr))
+        return step / launches_per_step
     return float("nan")
 
 
@@ -106,10 +122,10 @@ def mix_ceiling(name: str, N: int, limbs: int, polys: int, rates: dict) -> float
     return alg_ops(name, N, limbs, polys) / secs / 1e12
 
 
-# The sources the reported row kernel is compiled from: the counter summary
+# The sources the reported kernels are compiled from: the counter summary
 # stays valid while these are unchanged (host-only files do not matter).
 ROW_KERNEL_SOURCES = ("modarith.hpp", "modarith32.hpp", "ntt_device.hpp", "ntt_row.hpp", "pm_internal.hpp",
-                      "row_kernel.inc", "row_12.hip")
+                      "row_kernel.inc", "row_12.hip", "pm_kernels.hip", "pipe_kernels.hip", "pm_pipe.hpp")
 
 
 def kernel_source_hash() -> str:
@@ -253,6 +269,25 @@ def mixed_batch(torch, lib, dev, launches=5):
             "batched_over_per_request": round(ms_plain / ms, 3)}
 
 
+def alternate(torch, stream, fns, blocks=4, per=10):
+    """Median ms per call of each function in `fns` ({name: fn}), timed in
+    alternating blocks of `per` calls (each block after 2 untimed calls), so
+    that clock and thermal drift fall on every variant alike."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t = {k: [] for k in fns}
+    for _ in range(blocks):
+        for k, fn in fns.items():
+            for _ in range(2):
+                fn()
+            e0.record(stream)
+            for _ in range(per):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t[k].append(e0.elapsed_time(e1) / per)
+    return {k: pct(v, 50) for k, v in t.items()}
+
+
 def _median_call_us(torch, stream, fn, reps):
     """Median device time of one call over `reps` back-to-back calls (events
     between consecutive calls on the same stream)."""
@@ -336,24 +371,41 @@ def words32(torch, lib, dev, steps=20):
     def step():
         lib.pm_polymul_u32(da, db, dc, N, L32, P, prm.q, prm.psi_br, prm.psi_inv_br, ws)
 
-    for _ in range(3):
+    def with_pipeline(chunks):
+        def fn():
+            lib.pm_tune_set_pipeline(chunks)
+            step()
+        return fn
+
+    def kernels(chunks):
+        lib.pm_tune_set_pipeline(chunks)
+        lib.pm_prof_read(reset=True)
+        lib.pm_prof_enable(True)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        lib.pm_prof_enable(False)
+        return lib.pm_prof_read(reset=True)
+
+    for _ in range(10):
         step()
-    lib.pm_prof_read(reset=True)
-    lib.pm_prof_enable(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    lib.pm_prof_enable(False)
-    k32 = lib.pm_prof_read(reset=True)
-    ms = e0.elapsed_time(e1) / steps
+    med = alternate(torch, stream, {"pipelined": with_pipeline(-1), "three_pass": with_pipeline(0)})
+    ms, ms3 = med["pipelined"], med["three_pass"]
+    k32, k3 = kernels(-1), kernels(0)
+    lib.pm_tune_set_pipeline(-1)
+    logr = N.bit_length() - 1 - 12
+
+    def step_ops(name):
+        # algorithmic ops of one step over all 96 limbs
+        if name.startswith("pipe32_mul"):
+            return sum(alg_ops(k, N, L32, P, OPS32[30])
+                       for k in ("row32_mul_c12", "col32_fwd_r%d" % logr, "col32_inv_r%d" % logr))
+        return alg_ops(name, N, L32, P, OPS32[30])
+
     dom = max(k32.items(), key=lambda kv: kv[1][1])[0]
-    _, dom_ms = k32[dom]
-    # algorithmic ops of one step: the moduli travel in chunks of 64 limbs per launch
-    ops = sum(alg_ops(dom, N, min(64, L32 - l0), P, OPS32[30]) for l0 in range(0, L32, 64))
-    achieved = ops * steps / (dom_ms / 1e3) / 1e12
+    achieved = step_ops(dom) * steps / (k32[dom][1] / 1e3) / 1e12
+    row3 = max(k3.items(), key=lambda kv: kv[1][1])[0]
+    achieved3 = step_ops(row3) * steps / (k3[row3][1] / 1e3) / 1e12
     x = da.clone()
     ntt_us = _median_call_us(torch, stream, lambda: lib.pm_ntt_fwd_u32(x, N, L32, P, prm.q, prm.psi_br), 20)
     return {"what": "32-bit words, moduli < 2^30 (Alg. 4, beta = 32)",
@@ -367,7 +419,12 @@ def words32(torch, lib, dev, steps=20):
                 "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                              "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
                              "frac": round(achieved / PEAK_VALU_TOPS, 4),
-                             "ops_per_unit": {"ct": OPS32[30][0], "gs": OPS32[30][1], "mul": OPS32[30][2]}}}}
+                             "ops_per_unit": {"ct": OPS32[30][0], "gs": OPS32[30][1], "mul": OPS32[30][2]}},
+                "timing": "median of 4 alternating blocks of 10 steps, pipelined and three-pass",
+                "three_pass": {"ms_per_step": round(ms3, 4),
+                               "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(k3.items())},
+                               "row_pass": {"kernel": row3, "achieved": round(achieved3, 3),
+                                            "frac": round(achieved3 / PEAK_VALU_TOPS, 4)}}}}
 
 
 def valu_issue(lib):
@@ -517,23 +574,55 @@ def main():
     kern = lib.pm_prof_read(reset=True)
     timed_step_ms = e0.elapsed_time(e1) / args.steps
 
-    # ---- roofline of the dominant kernel
-    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
-    launches, dom_ms = kern[dom]
-    dom_avg_s = dom_ms / launches / 1e3
-    ops = alg_ops(dom, N, LIMBS, POLYS)
-    achieved = ops / dom_avg_s / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
-                "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
-                "traffic": measured_traffic(dom), "kernel": dom,
-                "kernel_avg_ms": round(dom_avg_s * 1e3, 4),
-                "alg_ops_per_launch": ops}
-    # the issue ceiling measured live (after the timed regions): the rates of
-    # the butterflies' instruction classes and the shader clock under load
+    # ---- the same step without software pipelining (three passes: column,
+    # row, column), for the row pass's own roofline
+    def with_pipeline(chunks):
+        def fn():
+            lib.pm_tune_set_pipeline(chunks)
+            step()
+        return fn
+
+    med = alternate(torch, stream, {"pipelined": with_pipeline(-1), "three_pass": with_pipeline(0)})
+    lib.pm_tune_set_pipeline(0)
+    lib.pm_prof_enable(True)
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    lib.pm_prof_enable(False)
+    kern3 = lib.pm_prof_read(reset=True)
+    lib.pm_tune_set_pipeline(-1)
+
+    # ---- roofline of the dominant kernel (the issue ceiling is measured live
+    # after the timed regions: the rates of the butterflies' instruction
+    # classes and the shader clock under load)
     issue = valu_issue(lib)
-    ceiling = mix_ceiling(dom, N, LIMBS, POLYS, {k: v * 1e12 for k, v in issue["lane_ops_T"].items()})
-    roofline["peak_mix_measured"] = round(ceiling, 3)
-    roofline["frac_of_mix_measured"] = round(achieved / ceiling, 4)
+    rates = {k: v * 1e12 for k, v in issue["lane_ops_T"].items()}
+
+    def kernel_roofline(kt, name):
+        launches, ms = kt[name]
+        avg_s = ms / launches / 1e3
+        ops = alg_ops(name, N, LIMBS, POLYS, launches_per_step=launches // args.steps)
+        achieved = ops / avg_s / 1e12
+        ceiling = mix_ceiling(name, N, LIMBS, POLYS, rates)
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
+                "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                "traffic": measured_traffic(name), "kernel": name,
+                "kernel_avg_ms": round(avg_s * 1e3, 4), "launches_per_step": launches // args.steps,
+                "alg_ops_per_launch": ops, "peak_mix_measured": round(ceiling, 3),
+                "frac_of_mix_measured": round(achieved / ceiling, 4)}
+
+    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
+    roofline = kernel_roofline(kern, dom)
+    row3 = max(kern3.items(), key=lambda kv: kv[1][1])[0]
+    three_pass = {"ms_per_step": round(med["three_pass"], 4),
+                  "value": round(products / med["three_pass"] * 1e3, 1), "unit": "polymul/s",
+                  "pipelined_ms_per_step_alternating": round(med["pipelined"], 4),
+                  "pipelined_over_three_pass": round(med["three_pass"] / med["pipelined"], 4),
+                  "timing": "median of 4 alternating blocks of 10 steps, pipelined and three-pass",
+                  "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(kern3.items())},
+                  "row_pass_roofline": kernel_roofline(kern3, row3),
+                  "what": "the same step with pm_tune_set_pipeline(0): column pass, row pass, "
+                          "column pass as three launches"}
     # HBM view of the whole step: operands and result once, tables once per limb
     b_alg = products * 24 * N + LIMBS * 16 * N
     hbm = {"alg_bytes_per_step": b_alg,
@@ -555,6 +644,7 @@ def main():
         "latency_ms": {"p50": round(pct(step_ms, 50), 4), "p99": round(pct(step_ms, 99), 4),
                        "unit": "per batched step of 384 products"},
         "roofline": roofline,
+        "three_pass": three_pass,
         "valu_issue": issue,
         "hbm_roofline": hbm,
         "kernels_avg_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(kern.items())},

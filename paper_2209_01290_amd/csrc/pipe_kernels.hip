@@ -1,6 +1,6 @@
 // Software-pipelined Eq. 2 (and the fused product of Alg. 8) over limb
 // chunks: the throughput plan with rows of 2^12 words after a column pass of
-// 2^3..2^5 rows (N = 2^15..2^17), 64-bit words.
+// 2^3..2^5 rows (N = 2^15..2^17), 64- or 32-bit words.
 //
 // The column passes are bound by memory and the row pass by the VALU. With
 // the batch split into G chunks of limbs, launch j runs three independent
@@ -31,10 +31,10 @@ static_assert(PG::WG == 256 && PG::ROWS == 1, "one 2^12-word row per workgroup o
 constexpr uint32_t PIPE_CB = (1u << PIPE_LC) / 256;   // column blocks of 256 per polynomial
 
 // grid: nr row workgroups, then nf forward-column and ni inverse-column ones.
-template <int LOGR, int KIND, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
-k_pipe(PipeArgs a, LimbSet ls) {
-  __shared__ uint64_t lds[PG::LDS_WORDS];
+template <typename W, int LOGR, int KIND, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowWaves<MODE>::value, 8)))
+k_pipe(PipeArgsT<W> a, LimbSetT<W> ls) {
+  __shared__ W lds[PG::LDS_WORDS];
   constexpr uint32_t R = 1u << LOGR;
   const size_t N = (size_t)1 << (PIPE_LC + LOGR), C = (size_t)1 << PIPE_LC;
   const uint32_t t = threadIdx.x, b = blockIdx.x;
@@ -42,7 +42,7 @@ k_pipe(PipeArgs a, LimbSet ls) {
     const uint32_t per_limb = a.polys * R;
     const uint32_t limb = a.rl0 + b / per_limb, task = b % per_limb;
     const size_t off = (size_t)limb * a.polys * N + ((size_t)task << PIPE_LC);
-    const Mod M = ls.mod[limb];
+    const typename ModOf<W>::type M = ls.mod[limb];
     row_task<PIPE_LC, KIND, MODE>(a.C + off, a.WS + off, a.C + off, a.twf + (size_t)limb * N,
                                   a.twi + (size_t)limb * N, R + (task & (R - 1)), true, M, lds, t);
     return;
@@ -58,10 +58,10 @@ k_pipe(PipeArgs a, LimbSet ls) {
   const uint32_t poly = rest % a.polys;
   const uint32_t limb = (fwd ? a.fl0 : a.il0) + rest / a.polys;
   const size_t off = ((size_t)limb * a.polys + poly) * N + (size_t)cb * 256 + t;
-  const uint64_t* src = fwd ? (op ? a.B : a.A) + off : a.C + off;
-  uint64_t* dst = fwd ? (op ? a.WS : a.C) + off : a.C + off;
-  const Mod M = ls.mod[limb];
-  uint64_t x[R];
+  const W* src = fwd ? (op ? a.B : a.A) + off : a.C + off;
+  W* dst = fwd ? (op ? a.WS : a.C) + off : a.C + off;
+  const typename ModOf<W>::type M = ls.mod[limb];
+  W x[R];
 #pragma unroll
   for (uint32_t i = 0; i < R; ++i) x[i] = src[i * C];
   if (fwd) col_fwd<LOGR, KIND>(x, a.twf + (size_t)limb * N, M);
@@ -70,29 +70,44 @@ k_pipe(PipeArgs a, LimbSet ls) {
   for (uint32_t i = 0; i < R; ++i) dst[i * C] = x[i];
 }
 
-template <int LOGR, int MODE>
-void pipe_launch(const PipeArgs& a, const LimbSet& ls, int kind, hipStream_t s) {
+template <typename W, int LOGR, int MODE>
+void pipe_launch(const PipeArgsT<W>& a, const LimbSetT<W>& ls, int kind, hipStream_t s) {
   const uint32_t blocks = a.nr + a.nf + a.ni;
-  if (kind == KIND_WIDE) hipLaunchKernelGGL((k_pipe<LOGR, KIND_WIDE, MODE>), dim3(blocks), dim3(256), 0, s, a, ls);
-  else hipLaunchKernelGGL((k_pipe<LOGR, KIND_ANY, MODE>), dim3(blocks), dim3(256), 0, s, a, ls);
+  if (kind == KIND_WIDE)
+    hipLaunchKernelGGL((k_pipe<W, LOGR, KIND_WIDE, MODE>), dim3(blocks), dim3(256), 0, s, a, ls);
+  else
+    hipLaunchKernelGGL((k_pipe<W, LOGR, KIND_ANY, MODE>), dim3(blocks), dim3(256), 0, s, a, ls);
 }
 
-template <int MODE>
-hipError_t pipe_launch_logr(int logr, const PipeArgs& a, const LimbSet& ls, int kind, hipStream_t s) {
+template <typename W, int MODE>
+hipError_t pipe_launch_logr(int logr, const PipeArgsT<W>& a, const LimbSetT<W>& ls, int kind, hipStream_t s) {
   switch (logr) {
-    case 3: pipe_launch<3, MODE>(a, ls, kind, s); break;
-    case 4: pipe_launch<4, MODE>(a, ls, kind, s); break;
-    case 5: pipe_launch<5, MODE>(a, ls, kind, s); break;
+    case 3: pipe_launch<W, 3, MODE>(a, ls, kind, s); break;
+    case 4: pipe_launch<W, 4, MODE>(a, ls, kind, s); break;
+    case 5: pipe_launch<W, 5, MODE>(a, ls, kind, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <typename W>
+hipError_t launch_pipe_any(int logr, bool fused, const PipeArgsT<W>& a, const LimbSetT<W>& ls, int kind,
+                           hipStream_t s) {
+  if (a.nr + a.nf + a.ni == 0) return hipSuccess;
+  return fused ? pipe_launch_logr<W, ROW_FMUL>(logr, a, ls, kind, s)
+               : pipe_launch_logr<W, ROW_MUL>(logr, a, ls, kind, s);
+}
+
 }  // namespace
 
-hipError_t launch_pipe(int logr, bool fused, const PipeArgs& a, const LimbSet& ls, int kind, hipStream_t s) {
-  if (a.nr + a.nf + a.ni == 0) return hipSuccess;
-  return fused ? pipe_launch_logr<ROW_FMUL>(logr, a, ls, kind, s) : pipe_launch_logr<ROW_MUL>(logr, a, ls, kind, s);
+hipError_t launch_pipe(int logr, bool fused, const PipeArgsT<uint64_t>& a, const LimbSetT<uint64_t>& ls, int kind,
+                       hipStream_t s) {
+  return launch_pipe_any(logr, fused, a, ls, kind, s);
+}
+
+hipError_t launch_pipe(int logr, bool fused, const PipeArgsT<uint32_t>& a, const LimbSetT<uint32_t>& ls, int kind,
+                       hipStream_t s) {
+  return launch_pipe_any(logr, fused, a, ls, kind, s);
 }
 
 }  // namespace pm

@@ -275,12 +275,14 @@ hipError_t run_pointwise(int kind, const uint64_t* A, const uint64_t* B, uint64_
   return launch_pointwise(kind, A, B, C, log2n, polys, limbs, ls, s);
 }
 
-// Calls f(limb0, nlimbs, LimbSetT<W>) for consecutive chunks of at most MAXL limbs.
+// Calls f(limb0, nlimbs, LimbSetT<W>) for consecutive launch groups of at
+// most ModOf<W>::maxl limbs.
 template <typename W, class F>
 int for_chunks(const BatchT<W>& b, F f) {
   LimbSetT<W> ls;
-  for (size_t l0 = 0; l0 < b.limbs; l0 += MAXL) {
-    const size_t nl = std::min((size_t)MAXL, b.limbs - l0);
+  constexpr size_t maxl = ModOf<W>::maxl;
+  for (size_t l0 = 0; l0 < b.limbs; l0 += maxl) {
+    const size_t nl = std::min(maxl, b.limbs - l0);
     std::memset(&ls, 0, sizeof(ls));
     for (size_t i = 0; i < nl; ++i) ls.mod[i] = b.mods[l0 + i];
     hipError_t e = f(l0, nl, ls);
@@ -394,7 +396,7 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
       return run_row(p.logc, b.kind, mode, ra, s, ebx);
     }
     // software-pipelined form: G chunks of limbs, G + 2 launches (pipe_kernels.hip)
-    if constexpr (sizeof(W) == 8) {
+    {
       uint32_t G = pipe_chunks(nl, polys);
       if (G > 1 && !same && p.ebx == 4 && p.logc == 12 && p.logr >= 3 && p.logr <= 5) {
         const uint32_t R = 1u << p.logr;
@@ -404,11 +406,12 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
         G = std::max<uint32_t>(G, (uint32_t)((nl + cap - 1) / cap));
         auto lo = [&](uint32_t k) { return (uint32_t)(k * nl / G); };   // chunk k = limbs [lo(k), lo(k+1))
         for (uint32_t j = 0; j < G + 2; ++j) {
-          PipeArgs pa{A + base, B + base, c + base, ws + base, tf, ti, (uint32_t)polys, 0, 0, 0, 0, 0, 0};
+          PipeArgsT<W> pa{A + base, B + base, c + base, ws + base, tf, ti, (uint32_t)polys, 0, 0, 0, 0, 0, 0};
           if (j >= 1 && j <= G) pa.rl0 = lo(j - 1), pa.nr = R * (uint32_t)polys * (lo(j) - lo(j - 1));
           if (j < G) pa.fl0 = lo(j), pa.nf = 32u * (uint32_t)polys * (lo(j + 1) - lo(j));
           if (j >= 2) pa.il0 = lo(j - 2), pa.ni = 16u * (uint32_t)polys * (lo(j - 1) - lo(j - 2));
-          ProfScope ps(s, fused ? "pipe_fmul_c12" : "pipe_mul_c12");
+          ProfScope ps(s, sizeof(W) == 8 ? (fused ? "pipe_fmul_c12" : "pipe_mul_c12")
+                                         : (fused ? "pipe32_fmul_c12" : "pipe32_mul_c12"));
           hipError_t e = launch_pipe((int)p.logr, fused, pa, ls, b.kind, s);
           if (e != hipSuccess) return e;
         }

@@ -9,18 +9,21 @@
 
 namespace pm {
 
-// Moduli of up to MAXL limbs travel by value in the kernel arguments; larger
-// batches are launched in chunks of MAXL limbs. Word types: uint64_t (q < 2^62,
-// constants in Mod) and uint32_t (q < 2^30, constants in Mod32).
+// The moduli of a launch group travel by value in the kernel arguments
+// (at most 4 KiB per launch): up to 64 limbs of Mod (32 bytes) or 128 of Mod32
+// (24 bytes); larger batches are launched in groups of that many limbs. Word
+// types: uint64_t (q < 2^62, constants in Mod) and uint32_t (q < 2^30,
+// constants in Mod32).
 constexpr int MAXL = 64;
 
-template <typename W> struct ModOf { using type = Mod; };
-template <> struct ModOf<uint32_t> { using type = Mod32; };
+template <typename W> struct ModOf { using type = Mod; static constexpr int maxl = MAXL; };
+template <> struct ModOf<uint32_t> { using type = Mod32; static constexpr int maxl = 128; };
 
 template <typename W>
 struct LimbSetT {
-  typename ModOf<W>::type mod[MAXL];
+  typename ModOf<W>::type mod[ModOf<W>::maxl];
 };
+static_assert(sizeof(LimbSetT<uint64_t>) <= 2048 && sizeof(LimbSetT<uint32_t>) <= 3072, "kernel argument budget");
 using LimbSet = LimbSetT<uint64_t>;
 using LimbSet32 = LimbSetT<uint32_t>;
 

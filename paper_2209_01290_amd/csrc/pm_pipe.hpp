@@ -6,25 +6,29 @@
 
 namespace pm {
 
-// One pipelined launch over a batch [limb][poly][N], N = 2^(12 + logr),
-// rows of 2^12 words. Limb indices are those of the launch group's LimbSet:
+// One pipelined launch over a batch [limb][poly][N] of 64- or 32-bit words,
+// N = 2^(12 + logr), rows of 2^12 words. Limb indices are those of the launch group's LimbSet:
 // rl0 / fl0 / il0 = first limb of the row, forward-column and inverse-column
 // chunk; nr / nf / ni = workgroups of each kind (0 when absent):
 // nr = 2^logr * polys * limbs (one per row), nf = 2 * 16 * polys * limbs (two
 // operands, 16 blocks of 256 columns per polynomial), ni = 16 * polys * limbs.
-struct PipeArgs {
-  const uint64_t* A;
-  const uint64_t* B;
-  uint64_t* C;                 // output; holds a's column-pass result in between
-  uint64_t* WS;                // workspace: b's column-pass result
-  const uint64_t* twf;         // psi_br [limbs][N]
-  const uint64_t* twi;         // psi_inv_br [limbs][N]
+template <typename W>
+struct PipeArgsT {
+  const W* A;
+  const W* B;
+  W* C;                        // output; holds a's column-pass result in between
+  W* WS;                       // workspace: b's column-pass result
+  const W* twf;                // psi_br [limbs][N]
+  const W* twi;                // psi_inv_br [limbs][N]
   uint32_t polys;
   uint32_t rl0, fl0, il0;
   uint32_t nr, nf, ni;
 };
 
 // logr in 3..5; fused: Alg. 8's rows instead of Eq. 2's.
-hipError_t launch_pipe(int logr, bool fused, const PipeArgs& a, const LimbSet& ls, int kind, hipStream_t s);
+hipError_t launch_pipe(int logr, bool fused, const PipeArgsT<uint64_t>& a, const LimbSetT<uint64_t>& ls, int kind,
+                       hipStream_t s);
+hipError_t launch_pipe(int logr, bool fused, const PipeArgsT<uint32_t>& a, const LimbSetT<uint32_t>& ls, int kind,
+                       hipStream_t s);
 
 }  // namespace pm

@@ -170,3 +170,92 @@ def test_pipelined_benchmark_plan(L):
     fw_o, iv_o = oracle_tables(qs, N)
     want = oracle_polymul(a[:, :3], b[:, :3], qs, N, fw_o, iv_o)
     _assert_equal(got[:, :3], want, "tuned plan, first three pairs per limb")
+
+
+# ------------------------------------------------------------ 32-bit words --
+
+def _run32(L, fn, a, b, N, qs, dfw, div, chunks, alias=None):
+    import torch
+    limbs, polys = a.shape[0], a.shape[1]
+    da, db = L.to_device32(a), L.to_device32(b)
+    dc = {"a": da, "b": db}.get(alias) if alias else torch.empty_like(da)
+    nb = L.pm_polymul_u32_workspace_bytes(N, limbs, polys)
+    ws = torch.empty(nb // 4, dtype=torch.int32, device="cuda") if nb else None
+    L.pm_tune_set_pipeline(chunks)
+    L.pm_prof_enable(True)
+    try:
+        L.pm_prof_read()
+        fn(da, db, dc, N, limbs, polys, qs, dfw, div, ws)
+        _sync()
+        prof = {name: n for name, (n, _ms) in L.pm_prof_read().items()}
+    finally:
+        L.pm_prof_enable(False)
+        L.pm_tune_set_pipeline(-1)
+    return L.to_host32(dc).reshape(a.shape).astype(np.uint64), prof
+
+
+def _moduli32(L, N, bits_list):
+    qs = []
+    for bits in bits_list:
+        for q in L.pm_ntt_primes(N, 8, bits):
+            if q not in qs:
+                qs.append(q)
+                break
+    return qs
+
+
+# (log2 N, moduli bit lengths, polys, chunks)
+CASES32 = [
+    (15, [30, 30, 30], 3, 2), (16, [30, 29, 28], 2, 3), (16, [30] * 2, 32, -1), (17, [29, 30], 1, 2),
+]
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["eq2", "fused"])
+@pytest.mark.parametrize("log2n,bits,polys,chunks", CASES32)
+def test_pipelined_u32(L, log2n, bits, polys, chunks, fused):
+    N = 1 << log2n
+    L.pm_tune_set(L.OP_POLYMUL, log2n, 12)
+    qs = _moduli32(L, N, bits)
+    limbs = len(qs)
+    fw_o, iv_o = oracle_tables(qs, N)
+    fw = np.empty((limbs, N), np.uint32)
+    iv = np.empty((limbs, N), np.uint32)
+    for l, q in enumerate(qs):
+        fw[l], iv[l] = L.pm_make_tables_u32(q, N)
+    dfw, div = L.to_device32(fw), L.to_device32(iv)
+    a, b = operands(N, qs, polys, request=800 + log2n + polys)
+    fn = L.pm_polymul_fused_u32 if fused else L.pm_polymul_u32
+    got, prof = _run32(L, fn, a, b, N, qs, dfw, div, chunks)
+    G = min(chunks if chunks >= 0 else 2, limbs)
+    name = "pipe32_fmul_c12" if fused else "pipe32_mul_c12"
+    assert prof.get(name) == G + 2, "expected %d pipelined launches, saw %s" % (G + 2, prof)
+    _assert_equal(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "pipelined u32 N=%d" % N)
+    plain, prof0 = _run32(L, fn, a, b, N, qs, dfw, div, 0)
+    assert name not in prof0, prof0
+    _assert_equal(got, plain, "pipelined vs three-pass u32 N=%d" % N)
+    if not fused:
+        got_a, _ = _run32(L, fn, a, b, N, qs, dfw, div, chunks, alias="a")
+        _assert_equal(got_a, plain, "pipelined u32, c==a")
+
+
+def test_pipelined_u32_launch_groups(L):
+    """130 limbs of 32-bit words: launch groups of 128 and 2 limbs, each
+    pipelined on its own."""
+    N, limbs, polys = 1 << 15, 130, 1
+    L.pm_tune_set(L.OP_POLYMUL, 15, 12)
+    qs = L.pm_ntt_primes(N, limbs, 30)
+    assert len(qs) == limbs
+    fw = np.empty((limbs, N), np.uint32)
+    iv = np.empty((limbs, N), np.uint32)
+    for l, q in enumerate(qs):
+        fw[l], iv[l] = L.pm_make_tables_u32(q, N)
+    dfw, div = L.to_device32(fw), L.to_device32(iv)
+    a, b = operands(N, qs, polys, request=830)
+    got, prof = _run32(L, L.pm_polymul_u32, a, b, N, qs, dfw, div, 2)
+    assert prof.get("pipe32_mul_c12") == 2 * (2 + 2), prof
+    plain, _ = _run32(L, L.pm_polymul_u32, a, b, N, qs, dfw, div, 0)
+    _assert_equal(got, plain, "130 limbs pipelined vs three-pass")
+    sample = [0, 63, 64, 127, 128, 129]
+    fw_o, iv_o = oracle_tables([qs[l] for l in sample], N)
+    want = oracle_polymul(a[sample], b[sample], [qs[l] for l in sample], N, fw_o, iv_o)
+    _assert_equal(got[sample], want, "130 limbs, sampled limbs vs oracle")

@@ -172,8 +172,9 @@ def test_aliasing_u32(L, log2n, alias, fused):
 
 
 def test_many_limbs_chunked_u32(L):
+    """More limbs than one launch group holds (128 moduli for 32-bit words)."""
     import torch
-    N, limbs, polys = 1024, 70, 1
+    N, limbs, polys = 1024, 130, 1
     qs = L.pm_ntt_primes(N, limbs, 30)
     assert len(qs) == limbs
     fw_o, iv_o = oracle_tables(qs, N)
@@ -183,7 +184,7 @@ def test_many_limbs_chunked_u32(L):
     dc = torch.empty_like(da)
     L.pm_polymul_u32(da, db, dc, N, limbs, polys, qs, dfw, div, _ws(L, N, limbs, polys))
     _sync()
-    _eq(L.to_host32(dc).reshape(a.shape), oracle_polymul(a, b, qs, N, fw_o, iv_o), "70 limbs u32")
+    _eq(L.to_host32(dc).reshape(a.shape), oracle_polymul(a, b, qs, N, fw_o, iv_o), "130 limbs u32")
 
 
 @pytest.mark.parametrize("small_q,log2n", [(12289, 11), (7681, 8), (257, 7), (65537, 15), (97, 4), (17, 3)])
