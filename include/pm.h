@@ -274,16 +274,20 @@ int pm_tune_set_small_limit(int op, unsigned log2n, size_t max_words);
 size_t pm_tune_get_small_limit(int op, unsigned log2n);
 
 /*
- * Software-pipelined product: pm_polymul and pm_polymul_fused on 64-bit words
- * under a throughput plan with rows of 2^12 words and a column radix of
- * 2^3..2^5 (N = 2^15..2^17) split each launch group's limbs into G chunks
- * and run G + 2 launches; launch j does the row pass of chunk j-1, the forward
- * column pass of chunk j and the inverse column pass of chunk j-2, so that the
- * memory-bound column work overlaps the VALU-bound rows. chunks = -1 (the
- * default) pipelines batches of at least 64 products over 2 chunks; 0 or 1
- * never pipelines; G >= 2 uses G chunks (at most the limbs of a launch group;
- * more where a launch would exceed the grid limit). Results are identical
- * either way. Process-wide, read when a call is made; always PM_OK.
+ * Software-pipelined product: pm_polymul and pm_polymul_fused (64-bit
+ * words) and their _u32 forms, under a throughput plan with rows of 2^12
+ * words and a column radix of 2^3..2^5 (N = 2^15..2^17), split each launch
+ * group's products (limb-major) into G chunks and run G + 2 launches; launch
+ * j does the row pass of chunk j-1, the forward column pass of chunk j and
+ * the inverse column pass of chunk j-2, so that the memory-bound column work
+ * overlaps the VALU-bound rows. chunks = -1 (the default) pipelines a launch
+ * group over 2 chunks when its row pass has at least 2048 rows (8192 at
+ * N = 2^17), i.e. from 256 / 128 / 256 products at N = 2^15 / 2^16 / 2^17:
+ * each chunk's rows add a phase to the critical path, which pays only for
+ * batches that fill the GPU several times over; 0 or 1 never pipelines;
+ * G >= 2 uses G chunks (at most the group's products; more where a launch
+ * would exceed the grid limit). Results are identical either way.
+ * Process-wide, read when a call is made; always PM_OK.
  */
 int pm_tune_set_pipeline(int chunks);
 int pm_tune_get_pipeline(void);

@@ -1,9 +1,9 @@
-// Software-pipelined Eq. 2 (and the fused product of Alg. 8) over limb
-// chunks: the throughput plan with rows of 2^12 words after a column pass of
+// Software-pipelined Eq. 2 (and the fused product of Alg. 8) over chunks of
+// the batch's products: the throughput plan with rows of 2^12 words after a column pass of
 // 2^3..2^5 rows (N = 2^15..2^17), 64- or 32-bit words.
 //
 // The column passes are bound by memory and the row pass by the VALU. With
-// the batch split into G chunks of limbs, launch j runs three independent
+// the batch split into G chunks of products, launch j runs three independent
 // kinds of workgroup: the row pass of chunk j-1 (forward rows of a and b,
 // product, inverse rows), the forward column pass of chunk j and the inverse
 // column pass of chunk j-2. Their data are disjoint, and every dependency (a
@@ -31,6 +31,8 @@ static_assert(PG::WG == 256 && PG::ROWS == 1, "one 2^12-word row per workgroup o
 constexpr uint32_t PIPE_CB = (1u << PIPE_LC) / 256;   // column blocks of 256 per polynomial
 
 // grid: nr row workgroups, then nf forward-column and ni inverse-column ones.
+// A chunk is a range of products (limb-major: product p = limb * polys + poly,
+// stored at p * N), so a chunk may end inside a limb.
 template <typename W, int LOGR, int KIND, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowWaves<MODE>::value, 8)))
 k_pipe(PipeArgsT<W> a, LimbSetT<W> ls) {
@@ -39,12 +41,12 @@ k_pipe(PipeArgsT<W> a, LimbSetT<W> ls) {
   const size_t N = (size_t)1 << (PIPE_LC + LOGR), C = (size_t)1 << PIPE_LC;
   const uint32_t t = threadIdx.x, b = blockIdx.x;
   if (b < a.nr) {
-    const uint32_t per_limb = a.polys * R;
-    const uint32_t limb = a.rl0 + b / per_limb, task = b % per_limb;
-    const size_t off = (size_t)limb * a.polys * N + ((size_t)task << PIPE_LC);
+    const uint32_t prod = a.r0 + b / R, row = b % R;
+    const uint32_t limb = prod / a.polys;
+    const size_t off = (size_t)prod * N + ((size_t)row << PIPE_LC);
     const typename ModOf<W>::type M = ls.mod[limb];
     row_task<PIPE_LC, KIND, MODE>(a.C + off, a.WS + off, a.C + off, a.twf + (size_t)limb * N,
-                                  a.twi + (size_t)limb * N, R + (task & (R - 1)), true, M, lds, t);
+                                  a.twi + (size_t)limb * N, R + row, true, M, lds, t);
     return;
   }
   // column workgroups: forward (a -> C, b -> WS) or inverse (C in place)
@@ -52,12 +54,11 @@ k_pipe(PipeArgsT<W> a, LimbSetT<W> ls) {
   const uint32_t idx = fwd ? b - a.nr : b - a.nr - a.nf;
   const uint32_t nops = fwd ? 2u : 1u;
   const uint32_t cb = idx % PIPE_CB;
-  uint32_t rest = idx / PIPE_CB;
+  const uint32_t rest = idx / PIPE_CB;
   const uint32_t op = rest % nops;
-  rest /= nops;
-  const uint32_t poly = rest % a.polys;
-  const uint32_t limb = (fwd ? a.fl0 : a.il0) + rest / a.polys;
-  const size_t off = ((size_t)limb * a.polys + poly) * N + (size_t)cb * 256 + t;
+  const uint32_t prod = (fwd ? a.f0 : a.i0) + rest / nops;
+  const uint32_t limb = prod / a.polys;
+  const size_t off = (size_t)prod * N + (size_t)cb * 256 + t;
   const W* src = fwd ? (op ? a.B : a.A) + off : a.C + off;
   W* dst = fwd ? (op ? a.WS : a.C) + off : a.C + off;
   const typename ModOf<W>::type M = ls.mod[limb];

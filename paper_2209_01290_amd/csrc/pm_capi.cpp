@@ -344,15 +344,19 @@ size_t polymul_workspace(size_t N, size_t limbs, size_t polys) {
   return p.R > 1 ? N * limbs * polys * sizeof(W) : 0;
 }
 
-// Chunks of the software-pipelined product for a launch group of nl limbs
-// and polys pairs per limb: 2 for batches of at least PIPE_MIN_PRODUCTS
-// products, else 0 (the three-pass form), unless pm_tune_set_pipeline chose.
-// At most nl chunks.
-constexpr size_t PIPE_MIN_PRODUCTS = 64;
-uint32_t pipe_chunks(size_t nl, size_t polys) {
+// Chunks of the software-pipelined product for a launch group of np
+// products with a column radix of 2^logr, unless pm_tune_set_pipeline chose:
+// 2 when the row pass has at least PIPE_MIN_ROWS rows (PIPE_MIN_ROWS_R32 for
+// radix 32), else 0 (the three-pass form). Each chunk's rows are one more
+// phase on the critical path, and a row workgroup alone on its CU is bound by
+// latency, so the overlap pays only once the rows fill the CUs several times
+// over. At most np chunks.
+constexpr size_t PIPE_MIN_ROWS = 2048, PIPE_MIN_ROWS_R32 = 8192;
+uint32_t pipe_chunks(size_t np, uint32_t logr) {
   const int set = plan_pipe();
-  size_t g = set >= 0 ? (size_t)set : (nl * polys >= PIPE_MIN_PRODUCTS ? 2 : 0);
-  if (g > nl) g = nl;
+  const size_t rows = np << logr;
+  size_t g = set >= 0 ? (size_t)set : (rows >= (logr >= 5 ? PIPE_MIN_ROWS_R32 : PIPE_MIN_ROWS) ? 2 : 0);
+  if (g > np) g = np;
   return g > 1 ? (uint32_t)g : 0u;
 }
 
@@ -395,21 +399,22 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
                      (uint32_t)nl, &ls};
       return run_row(p.logc, b.kind, mode, ra, s, ebx);
     }
-    // software-pipelined form: G chunks of limbs, G + 2 launches (pipe_kernels.hip)
+    // software-pipelined form: G chunks of products, G + 2 launches (pipe_kernels.hip)
     {
-      uint32_t G = pipe_chunks(nl, polys);
+      const size_t np = nl * polys;     // products of this launch group
+      uint32_t G = pipe_chunks(np, p.logr);
       if (G > 1 && !same && p.ebx == 4 && p.logc == 12 && p.logr >= 3 && p.logr <= 5) {
         const uint32_t R = 1u << p.logr;
-        // a launch holds at most (R + 48) * polys * ceil(nl / G) workgroups;
-        // keep its grid under 2^32 threads
-        const size_t cap = (((size_t)1 << 24) - 1) / ((R + 48) * polys);
-        G = std::max<uint32_t>(G, (uint32_t)((nl + cap - 1) / cap));
-        auto lo = [&](uint32_t k) { return (uint32_t)(k * nl / G); };   // chunk k = limbs [lo(k), lo(k+1))
+        // a launch holds at most (R + 48) * ceil(np / G) workgroups; keep its
+        // grid under 2^32 threads
+        const size_t cap = (((size_t)1 << 24) - 1) / (R + 48);
+        G = std::max<uint32_t>(G, (uint32_t)((np + cap - 1) / cap));
+        auto lo = [&](uint32_t k) { return (uint32_t)(k * np / G); };   // chunk k = products [lo(k), lo(k+1))
         for (uint32_t j = 0; j < G + 2; ++j) {
           PipeArgsT<W> pa{A + base, B + base, c + base, ws + base, tf, ti, (uint32_t)polys, 0, 0, 0, 0, 0, 0};
-          if (j >= 1 && j <= G) pa.rl0 = lo(j - 1), pa.nr = R * (uint32_t)polys * (lo(j) - lo(j - 1));
-          if (j < G) pa.fl0 = lo(j), pa.nf = 32u * (uint32_t)polys * (lo(j + 1) - lo(j));
-          if (j >= 2) pa.il0 = lo(j - 2), pa.ni = 16u * (uint32_t)polys * (lo(j - 1) - lo(j - 2));
+          if (j >= 1 && j <= G) pa.r0 = lo(j - 1), pa.nr = R * (lo(j) - lo(j - 1));
+          if (j < G) pa.f0 = lo(j), pa.nf = 32u * (lo(j + 1) - lo(j));
+          if (j >= 2) pa.i0 = lo(j - 2), pa.ni = 16u * (lo(j - 1) - lo(j - 2));
           ProfScope ps(s, sizeof(W) == 8 ? (fused ? "pipe_fmul_c12" : "pipe_mul_c12")
                                          : (fused ? "pipe32_fmul_c12" : "pipe32_mul_c12"));
           hipError_t e = launch_pipe((int)p.logr, fused, pa, ls, b.kind, s);

@@ -1,17 +1,18 @@
 // Software-pipelined Eq. 2 and fused product (pipe_kernels.hip): one launch
-// runs the row pass of one limb chunk, the forward column pass of the next
-// chunk and the inverse column pass of the chunk before.
+// runs the row pass of one chunk of products, the forward column pass of the
+// next chunk and the inverse column pass of the chunk before.
 #pragma once
 #include "pm_internal.hpp"
 
 namespace pm {
 
 // One pipelined launch over a batch [limb][poly][N] of 64- or 32-bit words,
-// N = 2^(12 + logr), rows of 2^12 words. Limb indices are those of the launch group's LimbSet:
-// rl0 / fl0 / il0 = first limb of the row, forward-column and inverse-column
-// chunk; nr / nf / ni = workgroups of each kind (0 when absent):
-// nr = 2^logr * polys * limbs (one per row), nf = 2 * 16 * polys * limbs (two
-// operands, 16 blocks of 256 columns per polynomial), ni = 16 * polys * limbs.
+// N = 2^(12 + logr), rows of 2^12 words. A chunk is a range of products p =
+// limb * polys + poly (indices within the launch group): r0 / f0 / i0 = first
+// product of the row, forward-column and inverse-column chunk; nr / nf / ni =
+// workgroups of each kind (0 when absent): nr = 2^logr per product (one per
+// row), nf = 2 * 16 per product (two operands, 16 blocks of 256 columns),
+// ni = 16 per product.
 template <typename W>
 struct PipeArgsT {
   const W* A;
@@ -21,7 +22,7 @@ struct PipeArgsT {
   const W* twf;                // psi_br [limbs][N]
   const W* twi;                // psi_inv_br [limbs][N]
   uint32_t polys;
-  uint32_t rl0, fl0, il0;
+  uint32_t r0, f0, i0;
   uint32_t nr, nf, ni;
 };
 

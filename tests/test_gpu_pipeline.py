@@ -1,8 +1,9 @@
 """Parity of the software-pipelined product (needs an MI355X).
 
-pm_polymul and pm_polymul_fused on 64-bit words, with rows of 2^12 words and
-a column radix of 2^3..2^5, split each launch group's limbs into chunks and
-overlap the row pass of one chunk with the column passes of its neighbours.
+pm_polymul and pm_polymul_fused (64- and 32-bit words), with rows of 2^12
+words and a column radix of 2^3..2^5, split each launch group's products into
+chunks and overlap the row pass of one chunk with the column passes of its
+neighbours.
 Every case compares each output word with the oracle, and the pipelined
 result with the three-pass one (pm_tune_set_pipeline(0)) on the same inputs.
 """
@@ -63,12 +64,20 @@ def _run(L, fn, a, b, N, qs, dfw, div, chunks, alias=None):
     return L.to_host(dc).reshape(a.shape), prof
 
 
-# (log2 N, limbs, polys, chunks): chunks of unequal size, one limb per chunk,
-# more chunks asked for than limbs, the built-in choice at >= 64 products
+def auto_chunks(log2n, products):
+    """The built-in choice: 2 chunks from 2048 rows of 2^12 words (8192 for
+    N = 2^17), else the three-pass form."""
+    rows = products << (log2n - 12)
+    return 2 if rows >= (8192 if log2n >= 17 else 2048) else 0
+
+
+# (log2 N, limbs, polys, chunks): chunks of unequal size, chunks that end
+# inside a limb, one product per chunk, more chunks asked for than products,
+# one limb, the built-in choice below and at its threshold
 CASES = [
-    (15, 3, 4, 2), (15, 5, 2, 3), (15, 4, 1, 4), (15, 2, 3, 9),
-    (16, 3, 2, 2), (16, 2, 32, -1), (16, 5, 1, 5),
-    (17, 3, 1, 2), (17, 2, 2, 2),
+    (15, 3, 4, 2), (15, 5, 2, 3), (15, 3, 5, 4), (15, 4, 1, 4), (15, 2, 3, 9),
+    (16, 3, 2, 2), (16, 2, 32, -1), (16, 1, 128, -1), (16, 1, 7, 3), (16, 5, 1, 5),
+    (17, 3, 1, 2), (17, 2, 2, 2), (17, 1, 3, 2),
 ]
 
 
@@ -83,8 +92,12 @@ def test_pipelined_matches_oracle(L, log2n, limbs, polys, chunks, fused):
     a, b = operands(N, qs, polys, request=700 + 10 * log2n + limbs)
     fn = L.pm_polymul_fused if fused else L.pm_polymul
     got, prof = _run(L, fn, a, b, N, qs, dfw, div, chunks)
-    G = min(chunks if chunks >= 0 else 2, limbs)
+    G = min(chunks if chunks >= 0 else auto_chunks(log2n, limbs * polys), limbs * polys)
     name = "pipe_fmul_c12" if fused else "pipe_mul_c12"
+    if G < 2:          # the built-in choice keeps the three-pass form here
+        assert name not in prof, prof
+        _assert_equal(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "three-pass N=%d" % N)
+        return
     assert prof.get(name) == G + 2, "expected %d pipelined launches, saw %s" % (G + 2, prof)
     assert not any(k.startswith("col") for k in prof), prof
     _assert_equal(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "pipelined N=%d" % N)
@@ -158,8 +171,9 @@ def test_pipelined_launch_groups(L):
 
 
 def test_pipelined_benchmark_plan(L):
-    """The tuned plans at the benchmark's 2^16 shape pipeline by default."""
-    N, limbs, polys = 1 << 16, 2, 48
+    """The tuned plans pipeline the benchmark's 2^16 product by default (here
+    2 limbs x 64 pairs: 2048 rows)."""
+    N, limbs, polys = 1 << 16, 2, 64
     qs = L.pm_ntt_primes(N, limbs)
     _, _, dfw, div = device_tables(qs, N)
     a, b = operands(N, qs, polys, request=795)
@@ -206,7 +220,7 @@ def _moduli32(L, N, bits_list):
 
 # (log2 N, moduli bit lengths, polys, chunks)
 CASES32 = [
-    (15, [30, 30, 30], 3, 2), (16, [30, 29, 28], 2, 3), (16, [30] * 2, 32, -1), (17, [29, 30], 1, 2),
+    (15, [30, 30, 30], 3, 2), (16, [30, 29, 28], 2, 3), (16, [30] * 2, 64, -1), (17, [29, 30], 1, 2),
 ]
 
 
@@ -226,7 +240,7 @@ def test_pipelined_u32(L, log2n, bits, polys, chunks, fused):
     a, b = operands(N, qs, polys, request=800 + log2n + polys)
     fn = L.pm_polymul_fused_u32 if fused else L.pm_polymul_u32
     got, prof = _run32(L, fn, a, b, N, qs, dfw, div, chunks)
-    G = min(chunks if chunks >= 0 else 2, limbs)
+    G = min(chunks if chunks >= 0 else auto_chunks(log2n, limbs * polys), limbs * polys)
     name = "pipe32_fmul_c12" if fused else "pipe32_mul_c12"
     assert prof.get(name) == G + 2, "expected %d pipelined launches, saw %s" % (G + 2, prof)
     _assert_equal(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "pipelined u32 N=%d" % N)
