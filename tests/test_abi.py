@@ -237,3 +237,20 @@ def test_small_plan_table(L):
                 L.pm_tune_set_small(op, n, 0, 0)
                 L.pm_tune_set_small_limit(op, n, 0)
         L.pm_tune_set_small_batch(0)
+
+
+def test_pipeline_setting():
+    """pm_tune_set_pipeline: -1 (any negative) = built-in choice, 0/1 = off,
+    G >= 2 = G chunks; the workspace does not depend on it."""
+    from paper_2209_01290_amd import lib as L
+    L.load()
+    try:
+        assert L.pm_tune_get_pipeline() == -1
+        N = 1 << 16
+        ws = L.pm_polymul_workspace_bytes(N, 48, 8)
+        for g, want in [(0, 0), (1, 1), (3, 3), (-7, -1), (2, 2)]:
+            L.pm_tune_set_pipeline(g)
+            assert L.pm_tune_get_pipeline() == want
+            assert L.pm_polymul_workspace_bytes(N, 48, 8) == ws
+    finally:
+        L.pm_tune_set_pipeline(-1)
