@@ -1,6 +1,6 @@
 // Software-pipelined Eq. 2 (and the fused product of Alg. 8) over chunks of
-// the batch's products: the throughput plan with rows of 2^12 words after a column pass of
-// 2^3..2^5 rows (N = 2^15..2^17), 64- or 32-bit words.
+// the batch's products: the throughput plan with rows of 2^12 words after a
+// column pass of 2^3..2^5 rows (N = 2^15..2^17), 64- or 32-bit words.
 //
 // The column passes are bound by memory and the row pass by the VALU. With
 // the batch split into G chunks of products, launch j runs three independent
@@ -11,10 +11,8 @@
 // is between consecutive launches on one stream, so no workgroup ever waits
 // for another. The rows come first in each launch and the short column
 // workgroups after them, so the column work fills the CUs that the long row
-// workgroups leave idle as they finish. (Interleaving the kinds finely was
-// measured slower: row workgroups that start at scattered times next to
-// column workgroups lose the near-lockstep progress through their long,
-// fully unrolled code.) G + 2 launches per batch.
+// workgroups leave idle as they finish. (An order that interleaved the kinds
+// finely in the grid measured about 1.5x slower.) G + 2 launches per batch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -28,7 +26,10 @@ namespace {
 constexpr int PIPE_LC = 12;                        // row length 2^12 (16 words per thread)
 using PG = RowGeom<PIPE_LC>;
 static_assert(PG::WG == 256 && PG::ROWS == 1, "one 2^12-word row per workgroup of 256 threads");
-constexpr uint32_t PIPE_CB = (1u << PIPE_LC) / 256;   // column blocks of 256 per polynomial
+// column blocks of 256 per polynomial: the host sizes a chunk's forward-column
+// grid as 2 * PIPE_CB and its inverse-column grid as PIPE_CB per product
+constexpr uint32_t PIPE_CB = (1u << PIPE_LC) / 256;
+static_assert(PIPE_CB == 16, "pm_capi.cpp launches 32 forward- and 16 inverse-column workgroups per product");
 
 // grid: nr row workgroups, then nf forward-column and ni inverse-column ones.
 // A chunk is a range of products (limb-major: product p = limb * polys + poly,
