@@ -285,8 +285,8 @@ size_t pm_tune_get_small_limit(int op, unsigned log2n);
  * N = 2^17), i.e. from 256 / 128 / 256 products at N = 2^15 / 2^16 / 2^17:
  * each chunk's rows add a phase to the critical path, which pays only for
  * batches that fill the GPU several times over; 0 or 1 never pipelines;
- * G >= 2 uses G chunks (at most the group's products; more where a launch
- * would exceed the grid limit). Results are identical either way.
+ * G >= 2 uses G chunks (at most 64 and at most the group's products; more
+ * where a launch would exceed the grid limit). Results are identical either way.
  * Process-wide, read when a call is made; always PM_OK.
  */
 int pm_tune_set_pipeline(int chunks);

@@ -350,12 +350,13 @@ size_t polymul_workspace(size_t N, size_t limbs, size_t polys) {
 // radix 32), else 0 (the three-pass form). Each chunk's rows are one more
 // phase on the critical path, and a row workgroup alone on its CU is bound by
 // latency, so the overlap pays only once the rows fill the CUs several times
-// over. At most np chunks.
-constexpr size_t PIPE_MIN_ROWS = 2048, PIPE_MIN_ROWS_R32 = 8192;
+// over. At most PIPE_MAX_CHUNKS chunks and at most np.
+constexpr size_t PIPE_MIN_ROWS = 2048, PIPE_MIN_ROWS_R32 = 8192, PIPE_MAX_CHUNKS = 64;
 uint32_t pipe_chunks(size_t np, uint32_t logr) {
   const int set = plan_pipe();
   const size_t rows = np << logr;
   size_t g = set >= 0 ? (size_t)set : (rows >= (logr >= 5 ? PIPE_MIN_ROWS_R32 : PIPE_MIN_ROWS) ? 2 : 0);
+  if (g > PIPE_MAX_CHUNKS) g = PIPE_MAX_CHUNKS;
   if (g > np) g = np;
   return g > 1 ? (uint32_t)g : 0u;
 }

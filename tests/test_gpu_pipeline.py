@@ -73,9 +73,10 @@ def auto_chunks(log2n, products):
 
 # (log2 N, limbs, polys, chunks): chunks of unequal size, chunks that end
 # inside a limb, one product per chunk, more chunks asked for than products,
-# one limb, the built-in choice below and at its threshold
+# more than the 64 chunks allowed, one limb, the built-in choice below and at
+# its threshold
 CASES = [
-    (15, 3, 4, 2), (15, 5, 2, 3), (15, 3, 5, 4), (15, 4, 1, 4), (15, 2, 3, 9),
+    (15, 3, 4, 2), (15, 5, 2, 3), (15, 3, 5, 4), (15, 4, 1, 4), (15, 2, 3, 9), (15, 2, 40, 100),
     (16, 3, 2, 2), (16, 2, 32, -1), (16, 1, 128, -1), (16, 1, 7, 3), (16, 5, 1, 5),
     (17, 3, 1, 2), (17, 2, 2, 2), (17, 1, 3, 2),
 ]
@@ -92,7 +93,7 @@ def test_pipelined_matches_oracle(L, log2n, limbs, polys, chunks, fused):
     a, b = operands(N, qs, polys, request=700 + 10 * log2n + limbs)
     fn = L.pm_polymul_fused if fused else L.pm_polymul
     got, prof = _run(L, fn, a, b, N, qs, dfw, div, chunks)
-    G = min(chunks if chunks >= 0 else auto_chunks(log2n, limbs * polys), limbs * polys)
+    G = min(chunks if chunks >= 0 else auto_chunks(log2n, limbs * polys), 64, limbs * polys)
     name = "pipe_fmul_c12" if fused else "pipe_mul_c12"
     if G < 2:          # the built-in choice keeps the three-pass form here
         assert name not in prof, prof
@@ -240,7 +241,7 @@ def test_pipelined_u32(L, log2n, bits, polys, chunks, fused):
     a, b = operands(N, qs, polys, request=800 + log2n + polys)
     fn = L.pm_polymul_fused_u32 if fused else L.pm_polymul_u32
     got, prof = _run32(L, fn, a, b, N, qs, dfw, div, chunks)
-    G = min(chunks if chunks >= 0 else auto_chunks(log2n, limbs * polys), limbs * polys)
+    G = min(chunks if chunks >= 0 else auto_chunks(log2n, limbs * polys), 64, limbs * polys)
     name = "pipe32_fmul_c12" if fused else "pipe32_mul_c12"
     assert prof.get(name) == G + 2, "expected %d pipelined launches, saw %s" % (G + 2, prof)
     _assert_equal(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "pipelined u32 N=%d" % N)
