@@ -5,8 +5,8 @@
 // The column passes are bound by memory and the row pass by the VALU. With
 // the batch split into G chunks of products, launch j runs three independent
 // kinds of workgroup: the row pass of chunk j-1 (forward rows of a and b,
-// product, inverse rows), the forward column pass of chunk j and the inverse
-// column pass of chunk j-2. Their data are disjoint, and every dependency (a
+// product, inverse rows; one forward row transform when a = b), the forward
+// column pass of chunk j and the inverse column pass of chunk j-2. Their data are disjoint, and every dependency (a
 // chunk's rows after its forward columns, its inverse columns after its rows)
 // is between consecutive launches on one stream, so no workgroup ever waits
 // for another. The rows come first in each launch and the short column
@@ -27,15 +27,22 @@ constexpr int PIPE_LC = 12;                        // row length 2^12 (16 words 
 using PG = RowGeom<PIPE_LC>;
 static_assert(PG::WG == 256 && PG::ROWS == 1, "one 2^12-word row per workgroup of 256 threads");
 // column blocks of 256 per polynomial: the host sizes a chunk's forward-column
-// grid as 2 * PIPE_CB and its inverse-column grid as PIPE_CB per product
+// grid as nops * PIPE_CB and its inverse-column grid as PIPE_CB per product
 constexpr uint32_t PIPE_CB = (1u << PIPE_LC) / 256;
-static_assert(PIPE_CB == 16, "pm_capi.cpp launches 32 forward- and 16 inverse-column workgroups per product");
+static_assert(PIPE_CB == 16, "pm_capi.cpp launches 16 column workgroups per product and operand");
 
 // grid: nr row workgroups, then nf forward-column and ni inverse-column ones.
 // A chunk is a range of products (limb-major: product p = limb * polys + poly,
 // stored at p * N), so a chunk may end inside a limb.
+// Waves per SIMD the register budget is set for: the row modes' own budget,
+// and 3 with a 32-word column in registers (4 would spill it).
+template <int LOGR, int MODE>
+struct PipeWaves {
+  static constexpr int value = LOGR >= 5 ? 3 : RowWaves<MODE>::value;
+};
+
 template <typename W, int LOGR, int KIND, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowWaves<MODE>::value, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PipeWaves<LOGR, MODE>::value, 8)))
 k_pipe(PipeArgsT<W> a, LimbSetT<W> ls) {
   __shared__ W lds[PG::LDS_WORDS];
   constexpr uint32_t R = 1u << LOGR;
@@ -46,14 +53,15 @@ k_pipe(PipeArgsT<W> a, LimbSetT<W> ls) {
     const uint32_t limb = prod / a.polys;
     const size_t off = (size_t)prod * N + ((size_t)row << PIPE_LC);
     const typename ModOf<W>::type M = ls.mod[limb];
-    row_task<PIPE_LC, KIND, MODE>(a.C + off, a.WS + off, a.C + off, a.twf + (size_t)limb * N,
-                                  a.twi + (size_t)limb * N, R + row, true, M, lds, t);
+    const W* Bp = (MODE == ROW_SQR) ? nullptr : (a.nops == 1 ? a.C : a.WS) + off;
+    row_task<PIPE_LC, KIND, MODE>(a.C + off, Bp, a.C + off, a.twf + (size_t)limb * N, a.twi + (size_t)limb * N,
+                                  R + row, true, M, lds, t);
     return;
   }
   // column workgroups: forward (a -> C, b -> WS) or inverse (C in place)
   const bool fwd = b < a.nr + a.nf;
   const uint32_t idx = fwd ? b - a.nr : b - a.nr - a.nf;
-  const uint32_t nops = fwd ? 2u : 1u;
+  const uint32_t nops = fwd ? a.nops : 1u;
   const uint32_t cb = idx % PIPE_CB;
   const uint32_t rest = idx / PIPE_CB;
   const uint32_t op = rest % nops;
@@ -93,23 +101,28 @@ hipError_t pipe_launch_logr(int logr, const PipeArgsT<W>& a, const LimbSetT<W>& 
 }
 
 template <typename W>
-hipError_t launch_pipe_any(int logr, bool fused, const PipeArgsT<W>& a, const LimbSetT<W>& ls, int kind,
+hipError_t launch_pipe_any(int logr, int mode, const PipeArgsT<W>& a, const LimbSetT<W>& ls, int kind,
                            hipStream_t s) {
+  if (a.nops < 1 || a.nops > 2) return hipErrorInvalidValue;
   if (a.nr + a.nf + a.ni == 0) return hipSuccess;
-  return fused ? pipe_launch_logr<W, ROW_FMUL>(logr, a, ls, kind, s)
-               : pipe_launch_logr<W, ROW_MUL>(logr, a, ls, kind, s);
+  switch (mode) {
+    case ROW_MUL: return pipe_launch_logr<W, ROW_MUL>(logr, a, ls, kind, s);
+    case ROW_FMUL: return pipe_launch_logr<W, ROW_FMUL>(logr, a, ls, kind, s);
+    case ROW_SQR: return pipe_launch_logr<W, ROW_SQR>(logr, a, ls, kind, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_pipe(int logr, bool fused, const PipeArgsT<uint64_t>& a, const LimbSetT<uint64_t>& ls, int kind,
+hipError_t launch_pipe(int logr, int mode, const PipeArgsT<uint64_t>& a, const LimbSetT<uint64_t>& ls, int kind,
                        hipStream_t s) {
-  return launch_pipe_any(logr, fused, a, ls, kind, s);
+  return launch_pipe_any(logr, mode, a, ls, kind, s);
 }
 
-hipError_t launch_pipe(int logr, bool fused, const PipeArgsT<uint32_t>& a, const LimbSetT<uint32_t>& ls, int kind,
+hipError_t launch_pipe(int logr, int mode, const PipeArgsT<uint32_t>& a, const LimbSetT<uint32_t>& ls, int kind,
                        hipStream_t s) {
-  return launch_pipe_any(logr, fused, a, ls, kind, s);
+  return launch_pipe_any(logr, mode, a, ls, kind, s);
 }
 
 }  // namespace pm

@@ -404,21 +404,24 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
     {
       const size_t np = nl * polys;     // products of this launch group
       uint32_t G = pipe_chunks(np, p.logr);
-      if (G > 1 && !same && p.ebx == 4 && p.logc == 12 && p.logr >= 3 && p.logr <= 5) {
+      if (G > 1 && p.ebx == 4 && p.logc == 12 && p.logr >= 3 && p.logr <= 5) {
+        const uint32_t nops = same ? 1u : 2u;
         const uint32_t R = 1u << p.logr;
         // a launch holds at most (R + 48) * ceil(np / G) workgroups; keep its
-        // grid under 2^32 threads
+        // grid under 2^32 threads (a = b: fewer)
         const size_t cap = (((size_t)1 << 24) - 1) / (R + 48);
         G = std::max<uint32_t>(G, (uint32_t)((np + cap - 1) / cap));
         auto lo = [&](uint32_t k) { return (uint32_t)(k * np / G); };   // chunk k = products [lo(k), lo(k+1))
         for (uint32_t j = 0; j < G + 2; ++j) {
-          PipeArgsT<W> pa{A + base, B + base, c + base, ws + base, tf, ti, (uint32_t)polys, 0, 0, 0, 0, 0, 0};
+          PipeArgsT<W> pa{A + base, B + base, c + base, same ? c + base : ws + base, tf, ti, (uint32_t)polys,
+                          0, 0, 0, 0, 0, 0, nops};
           if (j >= 1 && j <= G) pa.r0 = lo(j - 1), pa.nr = R * (lo(j) - lo(j - 1));
-          if (j < G) pa.f0 = lo(j), pa.nf = 32u * (lo(j + 1) - lo(j));
+          if (j < G) pa.f0 = lo(j), pa.nf = 16u * nops * (lo(j + 1) - lo(j));
           if (j >= 2) pa.i0 = lo(j - 2), pa.ni = 16u * (lo(j - 1) - lo(j - 2));
-          ProfScope ps(s, sizeof(W) == 8 ? (fused ? "pipe_fmul_c12" : "pipe_mul_c12")
-                                         : (fused ? "pipe32_fmul_c12" : "pipe32_mul_c12"));
-          hipError_t e = launch_pipe((int)p.logr, fused, pa, ls, b.kind, s);
+          static const char* const names[2][3] = {{"pipe32_mul_c12", "pipe32_fmul_c12", "pipe32_sqr_c12"},
+                                                  {"pipe_mul_c12", "pipe_fmul_c12", "pipe_sqr_c12"}};
+          ProfScope ps(s, names[sizeof(W) == 8][mode == ROW_FMUL ? 1 : (mode == ROW_SQR ? 2 : 0)]);
+          hipError_t e = launch_pipe((int)p.logr, mode, pa, ls, b.kind, s);
           if (e != hipSuccess) return e;
         }
         return hipSuccess;

@@ -11,25 +11,28 @@ namespace pm {
 // limb * polys + poly (indices within the launch group): r0 / f0 / i0 = first
 // product of the row, forward-column and inverse-column chunk; nr / nf / ni =
 // workgroups of each kind (0 when absent): nr = 2^logr per product (one per
-// row), nf = 2 * 16 per product (two operands, 16 blocks of 256 columns),
-// ni = 16 per product.
+// row), nf = nops * 16 per product (nops operands, 16 blocks of 256
+// columns), ni = 16 per product. nops = 1 when a = b (squaring): the forward
+// column pass transforms a alone into C, and the rows read C for both.
 template <typename W>
 struct PipeArgsT {
   const W* A;
   const W* B;
   W* C;                        // output; holds a's column-pass result in between
-  W* WS;                       // workspace: b's column-pass result
+  W* WS;                       // workspace: b's column-pass result (nops = 2)
   const W* twf;                // psi_br [limbs][N]
   const W* twi;                // psi_inv_br [limbs][N]
   uint32_t polys;
   uint32_t r0, f0, i0;
   uint32_t nr, nf, ni;
+  uint32_t nops;
 };
 
-// logr in 3..5; fused: Alg. 8's rows instead of Eq. 2's.
-hipError_t launch_pipe(int logr, bool fused, const PipeArgsT<uint64_t>& a, const LimbSetT<uint64_t>& ls, int kind,
+// logr in 3..5; mode: ROW_MUL (Eq. 2), ROW_FMUL (Alg. 8's rows) or ROW_SQR
+// (Eq. 2 with a = b, one forward row transform).
+hipError_t launch_pipe(int logr, int mode, const PipeArgsT<uint64_t>& a, const LimbSetT<uint64_t>& ls, int kind,
                        hipStream_t s);
-hipError_t launch_pipe(int logr, bool fused, const PipeArgsT<uint32_t>& a, const LimbSetT<uint32_t>& ls, int kind,
+hipError_t launch_pipe(int logr, int mode, const PipeArgsT<uint32_t>& a, const LimbSetT<uint32_t>& ls, int kind,
                        hipStream_t s);
 
 }  // namespace pm

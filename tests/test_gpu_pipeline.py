@@ -274,3 +274,39 @@ def test_pipelined_u32_launch_groups(L):
     fw_o, iv_o = oracle_tables([qs[l] for l in sample], N)
     want = oracle_polymul(a[sample], b[sample], [qs[l] for l in sample], N, fw_o, iv_o)
     _assert_equal(got[sample], want, "130 limbs, sampled limbs vs oracle")
+
+
+@pytest.mark.parametrize("inplace", [False, True], ids=["c", "c==a==b"])
+@pytest.mark.parametrize("fused", [False, True], ids=["eq2", "fused"])
+@pytest.mark.parametrize("log2n", [15, 16, 17])
+def test_pipelined_squaring(L, log2n, fused, inplace):
+    """a = b: one forward column operand, the squaring rows (or the fused rows
+    reading c for both), no workspace."""
+    import torch
+    N, limbs, polys = 1 << log2n, 3, 2
+    L.pm_tune_set(L.OP_POLYMUL, log2n, 12)
+    qs = L.pm_ntt_primes(N, limbs)
+    fw_o, iv_o = oracle_tables(qs, N)
+    _, _, dfw, div = device_tables(qs, N)
+    a, _ = operands(N, qs, polys, request=850 + log2n)
+    fn = L.pm_polymul_fused if fused else L.pm_polymul
+    want = oracle_polymul(a, a, qs, N, fw_o, iv_o)
+    outs = []
+    for chunks in (2, 0):
+        da = L.to_device(a)
+        dc = da if inplace else torch.empty_like(da)
+        L.pm_tune_set_pipeline(chunks)
+        L.pm_prof_enable(True)
+        try:
+            L.pm_prof_read()
+            fn(da, da, dc, N, limbs, polys, qs, dfw, div, None)
+            _sync()
+            prof = {k: n for k, (n, _ms) in L.pm_prof_read().items()}
+        finally:
+            L.pm_prof_enable(False)
+            L.pm_tune_set_pipeline(-1)
+        name = "pipe_fmul_c12" if fused else "pipe_sqr_c12"
+        assert (prof.get(name) == 4) == (chunks == 2), prof
+        outs.append(L.to_host(dc).reshape(a.shape))
+    _assert_equal(outs[0], want, "pipelined squaring N=%d" % N)
+    _assert_equal(outs[0], outs[1], "pipelined vs three-pass squaring N=%d" % N)
