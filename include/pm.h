@@ -275,7 +275,7 @@ size_t pm_tune_get_small_limit(int op, unsigned log2n);
 
 /*
  * Software-pipelined product: pm_polymul and pm_polymul_fused (64-bit
- * words) and their _u32 forms, under a throughput plan with rows of 2^12
+ * words; a = b included) and their _u32 forms, under a throughput plan with rows of 2^12
  * words and a column radix of 2^3..2^5 (N = 2^15..2^17), split each launch
  * group's products (limb-major) into G chunks and run G + 2 launches; launch
  * j does the row pass of chunk j-1, the forward column pass of chunk j and
