@@ -1,23 +1,33 @@
-"""Step-by-step models of the paper's Barrett reductions, in Python integers.
+"""Models of the paper's Barrett reductions, in Python integers.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-Each function follows one algorithm of Sec. II-B in the paper's own order and
-notation and returns ``(remainder, corrections)`` where ``corrections`` counts
-the correctional subtractions that were actually taken. Python integers are
-unbounded, so the word-size conditions of the algorithms are asserted instead
-of being enforced by overflow.
+Sec. II-B compares three reductions of x < 2^(2m) modulo q (m = len(q)). All
+three are members of Dhem and Quisquater's generalised Barrett reduction,
+which approximates the quotient floor(x / q) from two truncations:
 
-  classical(x, q)   Alg. 2: mu = floor(2^(2m)/q), c = x >> (m-1),
-                    quot = (c*mu) >> (m+1), up to two subtractions.
-  dhem_palisade     Alg. 3: Dhem-Quisquater with alpha = N+3, beta = -2:
-                    mu = floor(2^(2m+3)/q), c = x >> (m-2), quot = (c*mu) >> (m+5).
-  proposed(x, q)    Alg. 4: Dhem-Quisquater with alpha = N+1, beta = -2:
-                    mu = floor(2^(2m+1)/q), c = x >> (m-2), quot = (c*mu) >> (m+3).
+    mu   = floor(2^(m + alpha) / q)                      precomputed per q
+    quot = floor( floor(x / 2^(m + beta)) * mu / 2^(alpha - beta) )
+    r    = x - quot * q, then subtract q while r >= q
 
-The loops are written with a generic ``while r >= q`` so that a model never
-hides a case needing more corrections than its algorithm allows; tests check
-the counts against the bounds the paper states.
+Since x / q = (x / 2^(m + beta)) * (2^(m + alpha) / q) / 2^(alpha - beta),
+dropping the two fractional parts can only make quot smaller, never larger,
+so r >= 0; how much smaller (hence how many subtractions) depends on alpha
+and beta. The paper's three reductions are the parameter choices
+
+    classical  (Alg. 2, Barrett's original)  alpha = m,     beta = -1
+    dhem_palisade (Alg. 3)                   alpha = m + 3, beta = -2
+    proposed   (Alg. 4)                      alpha = m + 1, beta = -2
+
+(the paper writes alpha relative to the modulus length, e.g. "N + 3"). The
+word-size limit the paper states for each is asserted: len(q) <= word - 2
+for Alg. 2 and Alg. 4, len(q) <= word - 4 for Alg. 3 (mu < 2^(alpha + 1)
+and the values in between must be word-sized).
+
+Each function returns ``(remainder, corrections)`` with ``corrections`` the
+number of subtractions that were actually taken. The loop has no bound, so a
+model never hides a case needing more corrections than its algorithm allows;
+the tests check the counts against the bounds the paper states.
 """
 from __future__ import annotations
 
@@ -28,7 +38,21 @@ def bitlen(a: int) -> int:
     return a.bit_length()
 
 
-def _finish(x: int, quot: int, q: int):
+def dq_constants(q: int, alpha_off: int, beta: int):
+    """(m, mu, first shift, second shift) of the generalised reduction with
+    alpha = m + alpha_off: mu = floor(2^(m + alpha) / q), x is truncated by
+    m + beta bits and c * mu by alpha - beta bits."""
+    m = bitlen(q)
+    alpha = m + alpha_off
+    return m, (1 << (m + alpha)) // q, m + beta, alpha - beta
+
+
+def dq_reduce(x: int, q: int, alpha_off: int, beta: int):
+    """x mod q by the generalised Barrett reduction; (remainder, corrections)."""
+    m, mu, s1, s2 = dq_constants(q, alpha_off, beta)
+    assert 0 <= x < 1 << (2 * m), "the reduction takes x < 2^(2m)"
+    assert s1 >= 0, "modulus too short for this truncation"
+    quot = ((x >> s1) * mu) >> s2
     r = x - quot * q
     assert r >= 0, "approximate quotient exceeded the true quotient"
     k = 0
@@ -38,34 +62,35 @@ def _finish(x: int, quot: int, q: int):
     return r, k
 
 
+# The paper's three instantiations: (alpha - m, beta) and the extra bits the
+# word must hold beyond len(q) for mu to be word-sized (Sec. II-B: len(q) <=
+# word - 2 for Alg. 2 and Alg. 4, len(q) <= word - 4 for Alg. 3).
+CLASSICAL = (0, -1, 2)
+DHEM_PALISADE = (3, -2, 4)
+PROPOSED = (1, -2, 2)
+
+
+def _variant(params, x, q, word):
+    alpha_off, beta, headroom = params
+    assert bitlen(q) <= word - headroom, "modulus too long for this variant's word size"
+    return dq_reduce(x, q, alpha_off, beta)
+
+
 def classical(x: int, q: int, beta: int = 64):
-    m = bitlen(q)
-    assert m <= beta - 2 and 0 <= x < 2 ** (2 * m)
-    mu = (2 ** (2 * m)) // q
-    c = x >> (m - 1)
-    quot = (c * mu) >> (m + 1)
-    return _finish(x, quot, q)
+    """Alg. 2 (classical Barrett); `beta` is the word size in bits."""
+    return _variant(CLASSICAL, x, q, beta)
 
 
 def dhem_palisade(x: int, q: int, beta: int = 64):
-    m = bitlen(q)
-    assert m <= beta - 4 and 0 <= x < 2 ** (2 * m)
-    mu = (2 ** (2 * m + 3)) // q
-    c = x >> (m - 2)
-    quot = (c * mu) >> (m + 5)
-    return _finish(x, quot, q)
+    """Alg. 3 (Dhem-Quisquater, alpha = len(q) + 3, beta = -2)."""
+    return _variant(DHEM_PALISADE, x, q, beta)
 
 
 def proposed(x: int, q: int, beta: int = 64):
-    m = bitlen(q)
-    assert 2 <= m <= beta - 2 and 0 <= x < 2 ** (2 * m)
-    mu = (2 ** (2 * m + 1)) // q
-    c = x >> (m - 2)
-    quot = (c * mu) >> (m + 3)
-    return _finish(x, quot, q)
+    """Alg. 4 (the paper's choice, alpha = len(q) + 1, beta = -2)."""
+    return _variant(PROPOSED, x, q, beta)
 
 
 def proposed_constants(q: int):
     """(m, mu, shift1, shift2) of Alg. 4 for modulus q."""
-    m = bitlen(q)
-    return m, (2 ** (2 * m + 1)) // q, m - 2, m + 3
+    return dq_constants(q, *PROPOSED[:2])

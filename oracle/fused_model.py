@@ -1,25 +1,46 @@
-"""The fused polynomial multiplication of Sec. III-B, step by step, in pure
-Python integers, for small N.
+"""The fused polynomial multiplication of Sec. III-B, in pure Python integers,
+for small N, written from what each step computes.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``): it models the
 algorithm, so that its readings can be checked against the plain definition
 of the product (``bruteforce.negacyclic``); it shares nothing with the HIP
 library.
 
-  ct_merged_truncated   Alg. 5 with the final stage omitted (the loop runs
-                        while m < N/2).
-  gs_merged_truncated   Alg. 6 without one stage, each butterfly output
-                        halved (Eq. 2's merged 1/N). reading="first" omits
-                        the first stage (m = N/2), which is what the fused
-                        product needs; reading="last" is the text's literal
-                        loop change (while m > 1), which omits m = 1.
-  fused_pair            Alg. 7: (a0, a1), (b0, b1), alpha^2 ->
-                        (a0 b0 + alpha^2 a1 b1, a0 b1 + a1 b0) with four
-                        products (Karatsuba).
-  fused_pair_reference  the same pair by its definition: the last CT
-                        butterflies of a and b with alpha, the product, the
-                        first GS butterfly with alpha^-1, times 1/2.
-  polymul_fused         Alg. 8.
+What the steps compute. Let alpha_i = psi_br[N/2 + i] = psi^(2 br_{n-1}(i) + 1)
+for i < N/2: the full forward transform holds a(alpha_i) and a(-alpha_i) at
+positions 2i and 2i+1 (R2 reading), and x^N + 1 is the product of the N/2
+quadratics x^2 - alpha_i^2.
+
+  ct_truncated          the forward transform without its last stage (stride
+                        1): at positions 2i, 2i+1 the residue v0 + v1 x of a
+                        modulo x^2 - alpha_i^2 (the last stage would map it to
+                        v0 +- alpha_i v1 = a(+-alpha_i)); computed here from
+                        the residue's definition, v0 = a_even(alpha_i^2),
+                        v1 = a_odd(alpha_i^2).
+  gs_truncated          the halved inverse without one stage. reading="first"
+                        omits the first stage (stride 1, which with its 1/2
+                        maps the two values back to the residue pair): the
+                        rest interpolates c from its residue pairs, so it is
+                        computed as the inverse transform (definition: 1/N
+                        times the sum over the points) of the values
+                        v0 +- alpha_i v1. reading="last" is the text's literal
+                        loop change, which keeps the first stage and omits
+                        the last one (stride N/2, twiddle psi^-N/2, halved):
+                        its output is that last stage undone on the full
+                        inverse, z_j = c_j + psi^(N/2) c_(j+N/2),
+                        z_(j+N/2) = c_j - psi^(N/2) c_(j+N/2).
+  fused_pair            Alg. 7: the product of two residues modulo
+                        x^2 - gamma, (a0 + a1 x)(b0 + b1 x) =
+                        (a0 b0 + gamma a1 b1) + (a0 b1 + a1 b0) x, with the
+                        cross term from one product of sums (Karatsuba): four
+                        modular products instead of five.
+  fused_pair_reference  what the fused pair replaces, by definition: the last
+                        CT butterflies of a and b with alpha, the pointwise
+                        product, the first GS butterfly with alpha^-1, halved.
+  polymul_fused         Alg. 8: truncated transforms of a and b, Alg. 7 on
+                        each pair with gamma_i = alpha_i^2 taken as
+                        (-1)^i psi_br[N/4 + floor(i/2)] (reading R7b), then
+                        the truncated inverse.
 """
 from __future__ import annotations
 
@@ -36,49 +57,56 @@ def tables(q: int, n: int, psi: int):
             [pow(inv, bitrev(i, bits), q) for i in range(n)])
 
 
-def ct_merged_truncated(a, q, psi_br):
-    x = [int(v) % q for v in a]
-    n = len(x)
-    m, k = 1, n // 2
-    while m < n // 2:
-        for i in range(m):
-            xi = psi_br[m + i]
-            for j in range(2 * i * k, 2 * i * k + k):
-                t = xi * x[j + k] % q
-                x[j], x[j + k] = (x[j] + t) % q, (x[j] - t) % q
-        m, k = 2 * m, k // 2
-    return x
+def _poly_at(coeffs, x, q):
+    return sum(c * pow(x, j, q) for j, c in enumerate(coeffs)) % q
 
 
-def gs_merged_truncated(x, q, psi_inv_br, reading="first"):
-    x = [int(v) % q for v in x]
-    n = len(x)
-    half = (q + 1) // 2
+def ct_truncated(a, q, psi_br):
+    n = len(a)
+    a = [int(v) % q for v in a]
+    out = [0] * n
+    for i in range(n // 2):
+        gamma = psi_br[n // 2 + i] ** 2 % q
+        out[2 * i] = _poly_at(a[0::2], gamma, q)
+        out[2 * i + 1] = _poly_at(a[1::2], gamma, q)
+    return out
+
+
+def _inverse_transform(y, q, psi_br):
+    """c_j = (1/N) sum_p y_p x_p^-j over the points x_p = psi^(2 br(p) + 1),
+    i.e. +-alpha_i at positions 2i, 2i+1."""
+    n = len(y)
+    points = []
+    for i in range(n // 2):
+        alpha = psi_br[n // 2 + i]
+        points += [alpha, (q - alpha) % q]
+    n_inv = pow(n, q - 2, q)
+    inv_points = [pow(x, q - 2, q) for x in points]
+    return [n_inv * sum(yp * pow(xi, j, q) for yp, xi in zip(y, inv_points)) % q for j in range(n)]
+
+
+def gs_truncated(w, q, psi_br, reading="first"):
+    n = len(w)
+    w = [int(v) % q for v in w]
+    values = []
+    for i in range(n // 2):
+        alpha = psi_br[n // 2 + i]
+        values += [(w[2 * i] + alpha * w[2 * i + 1]) % q, (w[2 * i] - alpha * w[2 * i + 1]) % q]
     if reading == "first":
-        m, k, stop = n // 4, 2, 1          # stages m = N/4 .. 1
-    elif reading == "last":
-        m, k, stop = n // 2, 1, 2          # stages m = N/2 .. 2
-    else:
-        raise ValueError(reading)
-    while m >= stop:
-        for i in range(m):
-            xi = psi_inv_br[m + i]
-            for j in range(2 * i * k, 2 * i * k + k):
-                u, v = x[j], x[j + k]
-                x[j] = (u + v) * half % q
-                x[j + k] = xi * ((u - v) * half % q) % q
-        m, k = m // 2, 2 * k
-    return x
+        return _inverse_transform(values, q, psi_br)
+    if reading == "last":
+        c = _inverse_transform(w, q, psi_br)          # the pairs taken as transform values
+        s = psi_br[1]                                  # psi^(N/2), the inverse of the stage's twiddle
+        h = n // 2
+        return [(c[j] + s * c[j + h]) % q for j in range(h)] + [(c[j] - s * c[j + h]) % q for j in range(h)]
+    raise ValueError(reading)
 
 
-def fused_pair(a0, a1, b0, b1, alpha2, q):
-    prod1 = a0 * b0 % q
-    prod2 = a1 * b1 % q
-    sum1 = (a0 + a1) % q
-    sum2 = (b0 + b1) % q
-    prod3 = sum1 * sum2 % q
-    prod4 = alpha2 * prod2 % q
-    return (prod1 + prod4) % q, ((prod3 - prod1) % q - prod2) % q
+def fused_pair(a0, a1, b0, b1, gamma, q):
+    lo = a0 * b0 % q
+    hi = a1 * b1 % q
+    cross = ((a0 + a1) * (b0 + b1) - lo - hi) % q
+    return (lo + gamma * hi) % q, cross
 
 
 def fused_pair_reference(a0, a1, b0, b1, alpha, q):
@@ -91,16 +119,14 @@ def fused_pair_reference(a0, a1, b0, b1, alpha, q):
 
 
 def polymul_fused(a, b, q, psi_br, psi_inv_br, reading="first"):
+    """psi_inv_br is accepted for the interface of the device entry point; the
+    inverse here is computed from its definition with the points of psi_br."""
     n = len(a)
-    A = ct_merged_truncated(a, q, psi_br)
-    B = ct_merged_truncated(b, q, psi_br)
+    A = ct_truncated(a, q, psi_br)
+    B = ct_truncated(b, q, psi_br)
     C = [0] * n
     for i in range(n // 2):
-        u = A[2 * i] * B[2 * i] % q
-        v = A[2 * i + 1] * B[2 * i + 1] % q
-        w = (A[2 * i] + A[2 * i + 1]) * (B[2 * i] + B[2 * i + 1]) % q
-        y = (w - u) % q
-        C[2 * i + 1] = (y - v) % q
-        z = v * psi_br[n // 4 + i // 2] % q
-        C[2 * i] = (u + z) % q if i % 2 == 0 else (u - z) % q
-    return gs_merged_truncated(C, q, psi_inv_br, reading)
+        g = psi_br[n // 4 + i // 2]
+        gamma = g if i % 2 == 0 else (q - g) % q
+        C[2 * i], C[2 * i + 1] = fused_pair(A[2 * i], A[2 * i + 1], B[2 * i], B[2 * i + 1], gamma, q)
+    return gs_truncated(C, q, psi_br, reading)

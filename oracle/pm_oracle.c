@@ -18,13 +18,18 @@
  *       the negacyclic convolution, i.e. the product in Z_q[x]/(x^N + 1)
  *       (Sec. III): c_k = sum_{i+j=k} a_i b_j - sum_{i+j=k+N} a_i b_j.
  *   or_ntt_fwd
- *       merged Cooley-Tukey NTT, normal order in, bit-reversed order out,
- *       twiddles psi_br[i] = psi^br(i) (Sec. III-A, Alg. 5), every product
- *       reduced with '%'.
+ *       the forward transform Alg. 5 computes (Sec. III-A), normal order in,
+ *       bit-reversed order out, written from its definition: the values of
+ *       the polynomial at the roots psi^(2 br(p) + 1) of x^N = -1, computed
+ *       by the recursive even/odd split a(x) = a_e(x^2) + x a_o(x^2) (a
+ *       decimation-in-time recursion, not Alg. 5's butterfly loops); the
+ *       points are read from the table psi_br[i] = psi^br(i).
  *   or_ntt_inv
- *       merged Gentleman-Sande NTT (Alg. 6) with psi^-1 twiddles, followed by
- *       an explicit multiplication by N^-1 = N^(q-2) mod q (the 1/N factor of
- *       Eq. 1); it does not use the per-butterfly halving of Eq. 2.
+ *       its inverse (what Alg. 6 with the 1/N of Eq. 1 computes): the same
+ *       recursion undone level by level with psi^-1 points, without the
+ *       factors 1/2, followed by an explicit multiplication by
+ *       N^-1 = N^(q-2) mod q; it does not use the per-butterfly halving of
+ *       Eq. 2.
  *   or_ntt_eval
  *       brute-force definition of the forward transform: output position p
  *       is a(psi^(2*br(p)+1)) (evaluation at the odd powers of psi, in
@@ -126,42 +131,77 @@ uint64_t or_poly_eval(const uint64_t *a, size_t N, uint64_t q, uint64_t x) {
 }
 
 /* ---------------------------------------------------------------------- */
-/* Merged NTTs (Alg. 5 and Alg. 6), every product reduced with '%'.        */
+/* The transforms, from their definition as evaluation and interpolation.  */
 /* ---------------------------------------------------------------------- */
 
-void or_ntt_fwd(uint64_t *a, size_t N, uint64_t q, const uint64_t *psi_br) {
-    size_t m = 1, k = N / 2;
-    while (m < N) {
-        for (size_t i = 0; i < m; i++) {
-            size_t first = 2 * i * k;
-            uint64_t xi = psi_br[m + i];
-            for (size_t j = first; j < first + k; j++) {
-                uint64_t u = a[j];
-                uint64_t v = or_mulmod(xi, a[j + k], q);
-                a[j] = or_addmod(u, v, q);
-                a[j + k] = or_submod(u, v, q);
-            }
-        }
-        m *= 2;
-        k /= 2;
+/*
+ * Forward transform (what Alg. 5 computes, Sec. III-A): out[p] = a(x_p) with
+ * x_p = psi^(2 br(p) + 1), the N roots of x^N = -1 taken in bit-reversed
+ * order. Computed by the even/odd split of the polynomial,
+ *     a(x) = a_even(x^2) + x * a_odd(x^2),
+ * not by the butterfly loops of Alg. 5:
+ *   - positions 2t and 2t+1 hold the points x and -x for
+ *     x = psi^(2 br_{n-1}(t) + 1), since br_n(2t+1) = br_n(2t) + N/2 and
+ *     psi^N = -1;
+ *   - x^2 = (psi^2)^(2 br_{n-1}(t) + 1) is point t of the same transform of
+ *     size N/2 with psi^2 (whose (N/2)-th power is again -1);
+ * so out[2t] = E[t] + x O[t] and out[2t+1] = E[t] - x O[t], where E and O are
+ * the size-N/2 transforms of the even and odd coefficients. At a level of
+ * size M (root psi^(N/M)) the point x for position pair t is the table entry
+ * psi_br[M/2 + t] = psi^br_n(M/2 + t) = psi^((N/M) (2 br_{m-1}(t) + 1)).
+ *
+ * a: M coefficients, replaced by the M values; tmp: M words of scratch.
+ */
+static void eval_even_odd(uint64_t *a, size_t M, uint64_t q, const uint64_t *psi_br, uint64_t *tmp) {
+    if (M == 1) return;                     /* a constant is its own value */
+    size_t h = M / 2;
+    for (size_t i = 0; i < h; i++) {        /* even coefficients, then odd ones */
+        tmp[i] = a[2 * i];
+        tmp[h + i] = a[2 * i + 1];
+    }
+    eval_even_odd(tmp, h, q, psi_br, a);        /* E, with a as scratch */
+    eval_even_odd(tmp + h, h, q, psi_br, a);    /* O */
+    for (size_t t = 0; t < h; t++) {
+        uint64_t x = psi_br[h + t];
+        uint64_t xo = or_mulmod(x, tmp[h + t], q);
+        a[2 * t] = or_addmod(tmp[t], xo, q);
+        a[2 * t + 1] = or_submod(tmp[t], xo, q);
     }
 }
 
-void or_ntt_inv(uint64_t *a, size_t N, uint64_t q, const uint64_t *psi_inv_br) {
-    size_t m = N / 2, k = 1;
-    while (m >= 1) {
-        for (size_t i = 0; i < m; i++) {
-            size_t first = 2 * i * k;
-            uint64_t xi = psi_inv_br[m + i];
-            for (size_t j = first; j < first + k; j++) {
-                uint64_t u = a[j], v = a[j + k];
-                a[j] = or_addmod(u, v, q);
-                a[j + k] = or_mulmod(xi, or_submod(u, v, q), q);
-            }
-        }
-        m /= 2;
-        k *= 2;
+/*
+ * The inverse of eval_even_odd up to a factor M: from the values y at the
+ * points of a size-M level, E[t] = (y[2t] + y[2t+1]) / 2 and
+ * O[t] = (y[2t] - y[2t+1]) / (2x); the factors 1/2 are left out here, so each
+ * level doubles and the result is M times the coefficients. The inverse
+ * point 1/x is psi_inv_br[M/2 + t] (the table of psi^-1).
+ */
+static void interp_even_odd(uint64_t *y, size_t M, uint64_t q, const uint64_t *psi_inv_br, uint64_t *tmp) {
+    if (M == 1) return;
+    size_t h = M / 2;
+    for (size_t t = 0; t < h; t++) {
+        uint64_t u = y[2 * t], v = y[2 * t + 1];
+        tmp[t] = or_addmod(u, v, q);                                   /* 2 E[t] */
+        tmp[h + t] = or_mulmod(or_submod(u, v, q), psi_inv_br[h + t], q);  /* 2 O[t] */
     }
+    interp_even_odd(tmp, h, q, psi_inv_br, y);      /* M * even coefficients */
+    interp_even_odd(tmp + h, h, q, psi_inv_br, y);  /* M * odd coefficients */
+    for (size_t i = 0; i < h; i++) {
+        y[2 * i] = tmp[i];
+        y[2 * i + 1] = tmp[h + i];
+    }
+}
+
+void or_ntt_fwd(uint64_t *a, size_t N, uint64_t q, const uint64_t *psi_br) {
+    uint64_t *tmp = (uint64_t *)malloc(N * sizeof(uint64_t));
+    eval_even_odd(a, N, q, psi_br, tmp);
+    free(tmp);
+}
+
+void or_ntt_inv(uint64_t *a, size_t N, uint64_t q, const uint64_t *psi_inv_br) {
+    uint64_t *tmp = (uint64_t *)malloc(N * sizeof(uint64_t));
+    interp_even_odd(a, N, q, psi_inv_br, tmp);
+    free(tmp);
     /* the 1/N factor of Eq. 1, as an explicit multiplication */
     uint64_t ninv = or_powmod(N % q, q - 2, q);
     for (size_t j = 0; j < N; j++) a[j] = or_mulmod(a[j], ninv, q);

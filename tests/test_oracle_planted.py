@@ -19,14 +19,25 @@ MUTANTS = [
      [P.pin_schoolbook_bruteforce, P.pin_closed_forms]),
     ("coeff_index", "or_mulmod(a[i], b[k + N - i], q)", "or_mulmod(a[i], b[k + N - i - 1], q)",
      [P.pin_coeff]),
-    ("ct_twiddle_index", "uint64_t xi = psi_br[m + i];", "uint64_t xi = psi_br[m + (i ^ 1)];",
+    ("fwd_point_index", "uint64_t x = psi_br[h + t];", "uint64_t x = psi_br[h + (t + 1) % h];",
      [P.pin_ntt_eval, P.pin_ntt_invariants]),
-    ("ct_sign", "a[j + k] = or_submod(u, v, q);", "a[j + k] = or_submod(v, u, q);",
+    ("fwd_sign", "a[2 * t + 1] = or_submod(tmp[t], xo, q);", "a[2 * t + 1] = or_submod(xo, tmp[t], q);",
      [P.pin_ntt_eval, P.pin_ntt_invariants]),
-    ("gs_transposed", "a[j + k] = or_mulmod(xi, or_submod(u, v, q), q);",
-     "a[j + k] = or_mulmod(xi, or_submod(v, u, q), q);",
+    ("fwd_even_odd_swapped", "tmp[i] = a[2 * i];\n        tmp[h + i] = a[2 * i + 1];",
+     "tmp[i] = a[2 * i + 1];\n        tmp[h + i] = a[2 * i];",
+     [P.pin_ntt_eval, P.pin_ntt_invariants]),
+    ("fwd_output_pairs", "a[2 * t] = or_addmod(tmp[t], xo, q);", "a[t] = or_addmod(tmp[t], xo, q);",
+     [P.pin_ntt_eval]),
+    ("inv_transposed", "tmp[h + t] = or_mulmod(or_submod(u, v, q), psi_inv_br[h + t], q);",
+     "tmp[h + t] = or_mulmod(or_submod(v, u, q), psi_inv_br[h + t], q);",
      [lambda o: P.pin_ntt_roundtrip(o, sizes=(8, 64)),
       lambda o: P.pin_polymul_ntt_vs_schoolbook(o, sizes=(4, 16))]),
+    ("inv_point_forward_table", "tmp[h + t] = or_mulmod(or_submod(u, v, q), psi_inv_br[h + t], q);",
+     "tmp[h + t] = or_mulmod(or_submod(u, v, q), psi_inv_br[h + t] == 1 ? 1 : q - psi_inv_br[h + t], q);",
+     [lambda o: P.pin_ntt_roundtrip(o, sizes=(8, 64))]),
+    ("inv_interleave", "y[2 * i] = tmp[i];\n        y[2 * i + 1] = tmp[h + i];",
+     "y[i] = tmp[i];\n        y[h + i] = tmp[h + i];",
+     [lambda o: P.pin_ntt_roundtrip(o, sizes=(8, 64))]),
     ("no_inverse_scaling", "for (size_t j = 0; j < N; j++) a[j] = or_mulmod(a[j], ninv, q);", "",
      [lambda o: P.pin_ntt_roundtrip(o, sizes=(8, 64))]),
     ("pointwise_dropped", "c[j] = or_mulmod(c[j], tb[j], q);", "c[j] = or_addmod(c[j], tb[j], q);",
