@@ -161,13 +161,37 @@ def pct(xs, p):
     return xs[i]
 
 
-def cpu_baseline(N, qs, a_host, b_host, gpu_c, budget_s=12.0):
+def host_cpus():
+    """CPUs this process may run on (its affinity mask, capped by the job's
+    OMP_NUM_THREADS share where one is set), the machine's CPU count and model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(avail, int(share)) if share.isdigit() and int(share) > 0 else avail
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"threads": max(1, threads), "affinity_cpus": avail, "nproc": os.cpu_count(),
+            "omp_num_threads": share or None, "cpu_model": model}
+
+
+def cpu_baseline(N, qs, a_host, b_host, gpu_c, run_s=2.5, runs=5):
     """The oracle (plain C, % reductions) on a bounded sample of the same
-    products, one product per thread over the host cores; checks the GPU's
-    outputs for the sampled pairs on the way."""
+    products: one product per thread over every CPU the job may use, `runs`
+    runs of about `run_s` seconds, median; and the same on one core. Checks
+    the GPU's outputs for the sampled pairs on the way."""
     import oracle
     o = oracle.default()
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    cpus = host_cpus()
+    threads = cpus["threads"]
     pairs = [(i % len(qs), (i // len(qs)) % a_host.shape[1]) for i in range(threads)]
     tables = {}
     for l, _ in pairs:
@@ -179,22 +203,27 @@ def cpu_baseline(N, qs, a_host, b_host, gpu_c, budget_s=12.0):
     t1 = time.perf_counter() - t0
     if not np.array_equal(c0, gpu_c[l0, p0]):
         raise SystemExit("GPU output differs from the oracle on limb %d pair %d" % (l0, p0))
-    reps = max(1, int(budget_s / max(t1, 1e-6) / 1.5))
 
-    def work(k):
-        l, p = pairs[k]
-        for _ in range(reps):
-            c = o.polymul_ntt(a_host[l, p], b_host[l, p], qs[l], *tables[l])
-        return k, c
+    def timed_run(nthreads, reps):
+        def work(k):
+            l, p = pairs[k]
+            for _ in range(reps):
+                c = o.polymul_ntt(a_host[l, p], b_host[l, p], qs[l], *tables[l])
+            return k, c
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(nthreads) as ex:
+            outs = list(ex.map(work, range(nthreads)))
+        wall = time.perf_counter() - t0
+        for k, c in outs:
+            l, p = pairs[k]
+            if not np.array_equal(c, gpu_c[l, p]):
+                raise SystemExit("GPU output differs from the oracle on limb %d pair %d" % (l, p))
+        return nthreads * reps / wall
 
-    t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(threads) as ex:
-        outs = list(ex.map(work, range(threads)))
-    wall = time.perf_counter() - t0
-    for k, c in outs:
-        l, p = pairs[k]
-        if not np.array_equal(c, gpu_c[l, p]):
-            raise SystemExit("GPU output differs from the oracle on limb %d pair %d" % (l, p))
+    reps = max(1, int(run_s / max(t1, 1e-6) / 1.3))
+    rates = [timed_run(threads, reps) for _ in range(runs)]
+    reps1 = max(1, int(0.5 / max(t1, 1e-6)))
+    rates1 = [timed_run(1, reps1) for _ in range(runs)]
     # context for the one-product case: the O(N^2) schoolbook and the NTT
     # route of the oracle for one N = 1024 product, one thread
     from paper_2209_01290_amd import synth
@@ -209,39 +238,71 @@ def cpu_baseline(N, qs, a_host, b_host, gpu_c, budget_s=12.0):
     t_ntt = time.perf_counter() - t0
     if not np.array_equal(s1, n1):
         raise SystemExit("oracle schoolbook and NTT products differ at N=1024")
-    return {"value": threads * reps / wall, "unit": "polymul/s", "cores": threads, "kind": "oracle",
-            "sample": "%d products of the N=2^16 workload (%d per thread, %d threads, limbs %s), "
-                      "textbook merged NTTs with %% reductions, gcc -O2; single-thread %.1f ms/product"
-                      % (threads * reps, reps, threads, sorted(set(l for l, _ in pairs)), 1e3 * t1),
+    return {"value": round(pct(rates, 50), 1), "unit": "polymul/s", "cores": threads, "kind": "oracle",
+            "sample": "N=2^16 products of the benchmark workload (limbs %s), %d per thread per run, "
+                      "%d threads, median of %d runs; oracle transforms with %% reductions, gcc -O2"
+                      % (sorted(set(l for l, _ in pairs)), reps, threads, runs),
+            "runs_polymul_s": [round(r, 1) for r in rates],
+            "single_core": {"value": round(pct(rates1, 50), 1), "unit": "polymul/s",
+                            "runs_polymul_s": [round(r, 1) for r in rates1], "products_per_run": reps1},
+            "host": cpus,
             "n1024_one_product_us": {"schoolbook": round(t_school * 1e6, 1), "ntt": round(t_ntt * 1e6, 1),
                                      "threads": 1}}
 
 
 def mixed_batch(torch, lib, dev, launches=5):
     """The batched mixed workload: 512 requests, N uniform on 2^12..2^17, 1..48
-    limbs, all in one plan (one graph launch), against one pm_polymul call
-    per request (same kernels, batched across limbs only)."""
+    limbs, all in one plan (one graph launch). Its default job table is the
+    software-pipelined one; the same batch as a three-pass table (one launch
+    per pass of Eq. 2) is timed in alternating blocks, and one pm_polymul call
+    per request (same kernels, batched across limbs only) beside both."""
     from paper_2209_01290_amd import workloads
     reqs = workloads.mixed_requests(220901290 + 4)
     mb = workloads.MixedBatch(reqs, 220901290 + 4, dev)
     work16 = sum((1 << n) * n for n, L in reqs for _ in range(L)) / float((1 << 16) * 16)
-    plan = lib.pm_plan_create(mb.jobs)
     stream = torch.cuda.current_stream(dev)
+    plans = {}
     try:
-        for _ in range(2):
-            lib.pm_plan_launch(plan)
+        for name, chunks in (("pipelined", -1), ("three_pass", 0)):
+            lib.pm_tune_set_jobs_pipeline(chunks)
+            plans[name] = lib.pm_plan_create(mb.jobs)
+        lib.pm_tune_set_jobs_pipeline(-1)
+        per = {k: [] for k in plans}
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
-        torch.cuda.synchronize()
-        ev[0].record(stream)
-        for k in range(launches):
-            lib.pm_plan_launch(plan)
-            ev[k + 1].record(stream)
-        torch.cuda.synchronize()
-        per = [ev[k].elapsed_time(ev[k + 1]) for k in range(launches)]
-        dev_bytes = lib.pm_plan_device_bytes(plan)
+        for _rep in range(2):
+            for name, plan in plans.items():
+                for _ in range(2):
+                    lib.pm_plan_launch(plan)
+                torch.cuda.synchronize()
+                ev[0].record(stream)
+                for k in range(launches):
+                    lib.pm_plan_launch(plan)
+                    ev[k + 1].record(stream)
+                torch.cuda.synchronize()
+                per[name] += [ev[k].elapsed_time(ev[k + 1]) for k in range(launches)]
+        dev_bytes = lib.pm_plan_device_bytes(plans["pipelined"])
+        # the pipelined plan's kernels, timed one by one (graph launch off:
+        # the same launches issued directly, each bracketed by events)
+        lib.pm_tune_set_jobs_pipeline(-1)
+        direct = lib.pm_plan_create(mb.jobs, 1)
+        try:
+            lib.pm_plan_launch(direct)
+            torch.cuda.synchronize()
+            lib.pm_prof_read(reset=True)
+            lib.pm_prof_enable(True)
+            for _ in range(2):
+                lib.pm_plan_launch(direct)
+            torch.cuda.synchronize()
+            lib.pm_prof_enable(False)
+            kern = lib.pm_prof_read(reset=True)
+        finally:
+            lib.pm_plan_destroy(direct)
     finally:
-        lib.pm_plan_destroy(plan)
-    ms = sum(per) / len(per)
+        lib.pm_tune_set_jobs_pipeline(-1)
+        for plan in plans.values():
+            lib.pm_plan_destroy(plan)
+    ms = pct(per["pipelined"], 50)
+    ms3 = pct(per["three_pass"], 50)
     maxws = max(lib.pm_polymul_workspace_bytes(1 << n, L, 1) for n, L in reqs)
     ws = torch.empty(max(maxws // 8, 1), dtype=torch.int64, device=dev)
 
@@ -258,15 +319,97 @@ def mixed_batch(torch, lib, dev, launches=5):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_plain = e0.elapsed_time(e1)
+    # algorithmic VALU work of the batch (the per-unit counts of the uniform
+    # step): butterflies of the three transforms and the pointwise products
+    ops = sum(L * (1 << n) * (n * (OPS_CT + OPS_GS / 2.0) + OPS_MUL) for n, L in reqs)
+    pipe_ms = sum(v[1] for k, v in kern.items() if k == "jobs_pipe_mul_c12") / 2.0
     return {"what": "512 requests, N uniform on 2^12..2^17, 1..48 limbs (%d limb-products), one plan "
                     "(HIP graph) launch per batch" % mb.products,
-            "products": mb.products, "ms_per_batch": round(ms, 3), "p99_ms": round(pct(per, 99), 3),
+            "products": mb.products, "ms_per_batch": round(ms, 3), "p99_ms": round(pct(per["pipelined"], 99), 3),
+            "timing": "median of 2 alternating blocks of %d launches per form" % launches,
             "value": round(mb.products / ms * 1e3, 1), "unit": "polymul/s",
             "n16_equivalent_per_s": round(work16 / ms * 1e3, 1),
+            "jobs_pipeline_chunks": lib.pm_tune_get_jobs_pipeline(),
+            "pipelined_launches": {k: v[0] // 2 for k, v in kern.items()},
+            "kernels_ms_per_batch": {k: round(v[1] / 2.0, 4) for k, v in sorted(kern.items())},
+            "valu": {"alg_ops_per_batch": ops, "achieved_T_step": round(ops / (ms / 1e3) / 1e12, 3),
+                     "achieved_T_pipe_kernels": round(ops / (pipe_ms / 1e3) / 1e12, 3) if pipe_ms else None,
+                     "peak_T": round(PEAK_VALU_TOPS, 3)},
+            "three_pass": {"ms_per_batch": round(ms3, 3), "n16_equivalent_per_s": round(work16 / ms3 * 1e3, 1),
+                           "pipelined_over_three_pass": round(ms3 / ms, 4)},
             "plan_device_bytes": dev_bytes,
             "per_request_ms": round(ms_plain, 3),
             "per_request_value": round(mb.products / ms_plain * 1e3, 1),
             "batched_over_per_request": round(ms_plain / ms, 3)}
+
+
+def config2(torch, lib, dev, steps=20):
+    """The paper's global-memory baseline shape: N = 2^14, 32 limbs (the 32
+    largest 60-bit primes q = 1 mod 2^15), one pair per limb, through the plain
+    per-stage path pm_polymul_stagewise (14 forward stage launches over a and
+    b, one pointwise launch, 14 halved inverse stage launches; each launch
+    covers all limbs), with the batched pm_polymul beside it. Per-pass HBM
+    rate from the library's event timer: algorithmic bytes per launch (the
+    words each launch reads and writes once) over its average duration."""
+    from paper_2209_01290_amd import synth
+    N, L, P = 1 << 14, 32, 1
+    prm = lib.Params(N, L, device=dev)
+    a, b = synth.operands(220901290 + 2, prm.q, P, N)
+    da, db = lib.to_device(a, dev), lib.to_device(b, dev)
+    dc = torch.empty_like(da)
+    sws = torch.empty(max(lib.pm_polymul_stagewise_workspace_bytes(N, L, P) // 8, 1), dtype=torch.int64,
+                      device=dev)
+    bws = torch.empty(max(lib.pm_polymul_workspace_bytes(N, L, P) // 8, 1), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    plain = lambda: lib.pm_polymul_stagewise(da, db, dc, N, L, P, prm.q, prm.psi_br, prm.psi_inv_br, sws)
+    batched = lambda: lib.pm_polymul(da, db, dc, N, L, P, prm.q, prm.psi_br, prm.psi_inv_br, bws)
+
+    def per_step(fn):
+        for _ in range(5):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(steps):
+            fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+
+    t_plain, t_batched = per_step(plain), per_step(batched)
+    lib.pm_prof_read(reset=True)
+    lib.pm_prof_enable(True)
+    for _ in range(steps):
+        plain()
+    torch.cuda.synchronize()
+    lib.pm_prof_enable(False)
+    kern = lib.pm_prof_read(reset=True)
+    words = L * P * N
+    # bytes each launch moves once: a stage reads and writes its operands
+    # (a and b forward, c inverse) and reads its limbs' twiddles; pointwise
+    # reads two operands and writes one (the plain path moves every word
+    # 2 x 29 times per step: no stage fusion)
+    tw = L * (N - 1) // 14 * 8          # twiddle words per stage launch, on average over the 14 stages
+    alg_bytes = {"stage_fwd": 2 * 2 * words * 8 + tw, "stage_inv": 2 * words * 8 + tw, "pointwise": 3 * words * 8}
+    passes = {}
+    for name, (n, ms) in sorted(kern.items()):
+        avg = ms / n
+        passes[name] = {"launches_per_step": n // steps, "avg_ms": round(avg, 5),
+                        "alg_bytes": alg_bytes.get(name),
+                        "GBps": round(alg_bytes[name] / (avg / 1e3) / 1e9, 1) if name in alg_bytes else None}
+    ms_plain, ms_b = sum(t_plain) / steps, sum(t_batched) / steps
+    b_alg = L * P * 24 * N + L * 16 * N
+    return {"what": "N=2^14, 32 limbs x 1 pair, 60-bit primes; pm_polymul_stagewise: one launch per stage "
+                    "(29 launches per step), each over all limbs",
+            "value": round(L * P / ms_plain * 1e3, 1), "unit": "polymul/s", "ms_per_step": round(ms_plain, 4),
+            "latency_ms": {"p50": round(pct(t_plain, 50), 4), "p99": round(pct(t_plain, 99), 4)},
+            "per_pass": passes,
+            "hbm_roofline": {"alg_bytes_per_step": b_alg,
+                             "frac": round(b_alg / (ms_plain / 1e3) / 1e9 / PEAK_HBM_GBPS, 4)},
+            "batched": {"value": round(L * P / ms_b * 1e3, 1), "unit": "polymul/s", "ms_per_step": round(ms_b, 4),
+                        "latency_ms": {"p50": round(pct(t_batched, 50), 4), "p99": round(pct(t_batched, 99), 4)},
+                        "what": "pm_polymul on the same batch (tuned plan)"},
+            "batched_over_plain": round(ms_plain / ms_b, 3)}
 
 
 def alternate(torch, stream, fns, blocks=4, per=10):
@@ -463,13 +606,14 @@ def single_polymul(torch, lib, dev):
     return out
 
 
-def serving(lib, rates=(5000.0, 20000.0, 50000.0), nreq=4000):
+def serving(lib, rates=(2000.0, 5000.0, 10000.0, 20000.0, 50000.0), nreq=10000):
     """The continuous-batching loop on Poisson arrivals (N in 2^13..2^17,
     1..60 limbs): throughput and p50/p99 latency per offered rate."""
     from paper_2209_01290_amd import serve
     res = serve.run_rates(rates, nreq, budget_gib=32.0, streams=3, verbose=False)
-    keep = ("offered_rate_req_s", "completed", "throughput_req_s", "throughput_polymul_s",
-            "throughput_n16_equiv_s", "latency_ms", "mean_batch_requests", "max_queue")
+    keep = ("offered_rate_req_s", "requests", "completed", "throughput_req_s", "throughput_polymul_s",
+            "throughput_n16_equiv_s", "latency_ms", "mean_batch_requests", "max_queue", "max_inflight_batches",
+            "arena_peak_bytes")
     return [{k: r[k] for k in keep} for r in res]
 
 
@@ -507,6 +651,14 @@ def main():
                     help="only measure the VALU issue rates and the shader clock under load")
     ap.add_argument("--words32-only", action="store_true",
                     help="run only the 32-bit word measurement (for counter runs on its kernels)")
+    ap.add_argument("--part", default="all", choices=("all", "mixed", "config2", "serving"),
+                    help="all: the full report; mixed / config2 / serving: only that leg "
+                         "(for counter runs on its kernels)")
+    ap.add_argument("--settle-s", type=float, default=2.0,
+                    help="seconds of untimed steps after the warm-up, before the timed region "
+                         "(lets the shader clock and power state reach steady state)")
+    ap.add_argument("--pipeline-chunks", type=int, default=-1,
+                    help="chunks of the software-pipelined step (-1: the library's choice; 0: three passes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the workload's limbs are independent and would be "
@@ -529,6 +681,16 @@ def main():
     if args.valu_probe:
         print(json.dumps({"valu_issue": valu_issue(lib)}), flush=True)
         return
+    if args.part == "mixed":
+        print(json.dumps({"mixed_batch": mixed_batch(torch, lib, dev, launches=args.steps)}), flush=True)
+        return
+    if args.part == "config2":
+        print(json.dumps({"config2": config2(torch, lib, dev, steps=args.steps)}), flush=True)
+        return
+    if args.part == "serving":
+        print(json.dumps({"serving": serving(lib)}), flush=True)
+        return
+    lib.pm_tune_set_pipeline(args.pipeline_chunks)
     N = 1 << N_LOG2
     prm = lib.Params(N, LIMBS, device=dev)
     qs = prm.q
@@ -545,6 +707,16 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # settle: untimed steps for a fixed time, so that the timed region starts
+    # at the steady-state clock (the first few ms of load run slower)
+    settle_steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < args.settle_s:
+        for _ in range(25):
+            step()
+        torch.cuda.synchronize()
+        settle_steps += 25
+    settle = {"seconds": round(time.perf_counter() - t0, 3), "steps": settle_steps,
+              "what": "untimed steps run for a fixed time after the warm-up steps, before the timed region"}
 
     # ---- timed region: K batched steps, one HIP event between steps
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -582,7 +754,7 @@ def main():
             step()
         return fn
 
-    med = alternate(torch, stream, {"pipelined": with_pipeline(-1), "three_pass": with_pipeline(0)})
+    med = alternate(torch, stream, {"pipelined": with_pipeline(args.pipeline_chunks), "three_pass": with_pipeline(0)})
     lib.pm_tune_set_pipeline(0)
     lib.pm_prof_enable(True)
     for k in range(args.steps):
@@ -590,7 +762,7 @@ def main():
     torch.cuda.synchronize()
     lib.pm_prof_enable(False)
     kern3 = lib.pm_prof_read(reset=True)
-    lib.pm_tune_set_pipeline(-1)
+    lib.pm_tune_set_pipeline(args.pipeline_chunks)
 
     # ---- roofline of the dominant kernel (the issue ceiling is measured live
     # after the timed regions: the rates of the butterflies' instruction
@@ -643,6 +815,9 @@ def main():
                    "tuned_entries": tuned},
         "latency_ms": {"p50": round(pct(step_ms, 50), 4), "p99": round(pct(step_ms, 99), 4),
                        "unit": "per batched step of 384 products"},
+        "step_ms": [round(x, 4) for x in step_ms],
+        "settle": settle,
+        "pipeline_chunks": lib.pm_tune_get_pipeline(),
         "roofline": roofline,
         "three_pass": three_pass,
         "valu_issue": issue,
@@ -732,11 +907,13 @@ def main():
         step()
         torch.cuda.synchronize()
         out["mixed_batch"] = mixed_batch(torch, lib, dev)
+        out["mixed_batch"]["over_uniform_step_n16_rate"] = round(out["mixed_batch"]["n16_equivalent_per_s"] / value, 4)
         out["single_polymul_n1024"] = single_polymul(torch, lib, dev)
         w32 = words32(torch, lib, dev)
         w32["polymul_96x30bit_limbs"]["vs_48x60bit_limbs_u64"] = round(
             w32["polymul_96x30bit_limbs"]["q2880_products_per_s"] / (value / LIMBS), 3)
         out["words32"] = w32
+        out["config2"] = config2(torch, lib, dev)
         out["serving"] = serving(lib)
 
     if not args.no_cpu:

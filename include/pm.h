@@ -292,6 +292,25 @@ size_t pm_tune_get_small_limit(int op, unsigned log2n);
 int pm_tune_set_pipeline(int chunks);
 int pm_tune_get_pipeline(void);
 
+/*
+ * Software pipelining of job tables (pm_polymul_jobs, pm_plan_create): a
+ * batch whose jobs of N >= 2^12 hold at least 2048 rows of 2^12 words runs
+ * those jobs with rows of 2^12 words, their products split into G chunks of
+ * about equal work (in job order; a boundary may fall inside a job, between
+ * two of its products), in G + 2 launches; launch j does the row pass of
+ * chunk j-1, the forward column pass of chunk j and the inverse column pass
+ * of chunk j-2, with any mix of sizes and moduli in one launch. Jobs of
+ * N < 2^12 run their single row pass in a launch before the pipeline.
+ * chunks = -1 (the default): G = rows / 8192 within [2, 16]; 0 or 1: never
+ * pipelined (three launches, one per pass of Eq. 2, with the tuned splits);
+ * G >= 2: G chunks (at most 256; more where a launch would exceed the grid
+ * limit), pipelined whenever the batch has such a job. Results are
+ * identical either way. Process-wide, read when a table is built
+ * (pm_polymul_jobs call, pm_plan_create); always PM_OK.
+ */
+int pm_tune_set_jobs_pipeline(int chunks);
+int pm_tune_get_jobs_pipeline(void);
+
 /* ------------------------------------------------------------- kernel timing
  * While enabled, every kernel the library launches is bracketed by two HIP
  * events recorded on the launch's own stream (the measurement a profiler

@@ -1,16 +1,26 @@
 // Batched entry points over a job table (include/pm.h: pm_plan_*,
 // pm_polymul_jobs). A job is `count` polynomial pairs sharing N and q; a
 // batch mixes jobs of any N and modulus. Every job runs the three passes of
-// Eq. 2 (forward columns, fused rows, inverse columns), each pass being one
-// launch over the work items of all jobs, so a whole batch is three (or up to
-// five, with tuned long rows) kernel launches whatever its mix.
+// Eq. 2 (forward columns, fused rows, inverse columns).
+//
+// Two forms:
+//   * three-pass: each pass is one launch over the work items of all jobs
+//     (three, or up to five with tuned long rows, launches whatever the mix);
+//   * software-pipelined (batches whose jobs of N >= 2^12 hold at least
+//     JOBS_PIPE_MIN_ROWS rows of 2^12 words): those jobs take rows of 2^12
+//     words, their products are split into G chunks of about equal work, and
+//     G + 2 launches of k_jobs_pipe each run one chunk's rows beside the
+//     column passes of its neighbours (so the memory-bound column work
+//     overlaps the VALU-bound rows); jobs of N < 2^12 run their single row
+//     pass in a three-pass launch before the pipeline.
 //
 // Device blob layout (built on the host, one copy to the device):
-//   [JobDev x njobs][item->job maps: colf, row12, row13, row14, coli]
+//   [JobDev x njobs][item->job maps, one per group]
 //   [pad to 256 B][b's column outputs of the two-pass jobs]
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -27,8 +37,9 @@ using namespace pm;
 
 namespace {
 
-constexpr int NGROUP = 5;   // colf, row12, row13, row14, coli
-enum { G_COLF = 0, G_ROW12 = 1, G_ROW13 = 2, G_ROW14 = 3, G_COLI = 4 };
+// maps: three-pass colf, row12, row13, row14, coli; pipelined rows, colf, coli
+constexpr int NGROUP = 8;
+enum { G_COLF = 0, G_ROW12 = 1, G_ROW13 = 2, G_ROW14 = 3, G_COLI = 4, G_PROW = 5, G_PCOLF = 6, G_PCOLI = 7 };
 
 struct Layout {
   std::vector<JobDev> jobs;            // device pointers patched once the base is known
@@ -37,18 +48,84 @@ struct Layout {
   size_t table_bytes;                  // jobs + maps
   size_t ws_off, ws_bytes;             // b's column outputs
   int kind;
+  std::vector<JobsPipeLaunch> pipe;    // launches of the pipelined jobs (empty: three-pass form only)
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Pipelined form: used from this many rows of 2^12 words (jobs of N >= 2^12);
+// chunks chosen by default as rows / JOBS_PIPE_ROWS_PER_CHUNK, within
+// [2, JOBS_PIPE_MAX_AUTO]; at most JOBS_PIPE_MAX_CHUNKS when set.
+constexpr uint64_t JOBS_PIPE_MIN_ROWS = 2048, JOBS_PIPE_ROWS_PER_CHUNK = 8192;
+constexpr uint32_t JOBS_PIPE_MAX_AUTO = 16, JOBS_PIPE_MAX_CHUNKS = 256;
+std::atomic<int> g_jobs_pipe{-1};
+
+// Splits the pipelined jobs' products into G chunks of about equal work
+// (rows x stages per product) and appends the G + 2 launches. A chunk
+// boundary inside a job falls between two of its products; each phase's items
+// of a product are contiguous, so a boundary is one item index per map.
+bool plan_pipeline(Layout* L, const std::vector<uint32_t>& pjobs, uint32_t G) {
+  struct Bound { uint64_t row, colf, coli; };
+  auto per_product = [&](const JobDev& J, uint64_t* rows, uint64_t* colf, uint64_t* coli) {
+    const uint64_t R = 1ull << J.logr;
+    *rows = R;
+    *colf = R > 1 ? 16ull * J.nops : 0;
+    *coli = R > 1 ? 16 : 0;
+  };
+  long double W = 0;
+  for (uint32_t j : pjobs) {
+    const JobDev& J = L->jobs[j];
+    W += (long double)J.count * (long double)((1ull << J.logr) * (12 + J.logr));
+  }
+  std::vector<Bound> B(G + 1);
+  B[0] = {0, 0, 0};
+  B[G] = {L->map[G_PROW].size(), L->map[G_PCOLF].size(), L->map[G_PCOLI].size()};
+  size_t k = 0;                 // index into pjobs
+  long double acc = 0;          // work of the jobs before pjobs[k]
+  for (uint32_t c = 1; c < G; ++c) {
+    const long double target = W * c / G;
+    while (k < pjobs.size()) {
+      const JobDev& J = L->jobs[pjobs[k]];
+      const long double w = (long double)((1ull << J.logr) * (12 + J.logr));
+      if (acc + w * J.count >= target) break;
+      acc += w * J.count;
+      ++k;
+    }
+    if (k == pjobs.size()) { B[c] = B[G]; continue; }
+    const JobDev& J = L->jobs[pjobs[k]];
+    const long double w = (long double)((1ull << J.logr) * (12 + J.logr));
+    uint64_t poly = (uint64_t)((target - acc) / w + 0.5L);
+    if (poly > J.count) poly = J.count;
+    uint64_t r, f, i;
+    per_product(J, &r, &f, &i);
+    B[c] = {J.first[PH_ROW] + poly * r, J.first[PH_COLF] + poly * f, J.first[PH_COLI] + poly * i};
+    for (int q = 0; q < 3; ++q) {         // keep boundaries monotone
+      uint64_t* cur = q == 0 ? &B[c].row : (q == 1 ? &B[c].colf : &B[c].coli);
+      const uint64_t prev = q == 0 ? B[c - 1].row : (q == 1 ? B[c - 1].colf : B[c - 1].coli);
+      if (*cur < prev) *cur = prev;
+    }
+  }
+  L->pipe.clear();
+  for (uint32_t j = 0; j < G + 2; ++j) {
+    JobsPipeLaunch pl{0, 0, 0, 0, 0, 0};
+    if (j >= 1 && j <= G) pl.r0 = (uint32_t)B[j - 1].row, pl.nr = (uint32_t)(B[j].row - B[j - 1].row);
+    if (j < G) pl.f0 = (uint32_t)B[j].colf, pl.nf = (uint32_t)(B[j + 1].colf - B[j].colf);
+    if (j >= 2) pl.i0 = (uint32_t)B[j - 2].coli, pl.ni = (uint32_t)(B[j - 1].coli - B[j - 2].coli);
+    const uint64_t blocks = (uint64_t)pl.nr + pl.nf + pl.ni;
+    if (blocks >= (1ull << 24)) return false;       // keep each grid under 2^32 threads
+    if (blocks) L->pipe.push_back(pl);
+  }
+  return true;
+}
 
 int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
   if (!jobs || njobs == 0) return set_error(PM_EINVAL, "empty job list");
   if (njobs > (1u << 24)) return set_error(PM_EINVAL, "too many jobs");
   L->jobs.assign(njobs, JobDev{});
   for (auto& m : L->map) m.clear();
+  L->pipe.clear();
   L->kind = KIND_WIDE;
-  size_t ws = 0;
-  std::vector<size_t> ws_job(njobs, 0);
+  uint64_t pipe_rows = 0;           // rows of 2^12 words of the jobs of N >= 2^12
   for (size_t j = 0; j < njobs; ++j) {
     const pm_job& in = jobs[j];
     const std::string tag = "job " + std::to_string(j) + ": ";
@@ -63,11 +140,8 @@ int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
     JobDev& J = L->jobs[j];
     make_mod(in.q, &J.mod);
     if (mod_kind(J.mod) != KIND_WIDE) L->kind = KIND_ANY;
-    PassPlan p = plan_for(OP_POLYMUL, in.log2n);
     J.log2n = in.log2n;
     J.count = in.count;
-    J.logc = p.logc;
-    J.logr = p.logr;
     // The product is commutative: when c aliases b, swap so that c can only alias a.
     const bool swap = (in.c == in.b && in.c != in.a);
     J.a = swap ? in.b : in.a;
@@ -76,31 +150,67 @@ int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
     J.tf = in.psi_br;
     J.ti = in.psi_inv_br;
     J.nops = (J.a == J.b) ? 1 : 2;
-    if (p.R > 1 && J.nops == 2) {
+    if (in.log2n >= 12) pipe_rows += (uint64_t)in.count << (in.log2n - 12);
+  }
+  const int set = g_jobs_pipe.load();
+  const bool pipelined = set != 0 && set != 1 && pipe_rows >= (set > 1 ? 1 : JOBS_PIPE_MIN_ROWS);
+  size_t ws = 0;
+  std::vector<size_t> ws_job(njobs, 0);
+  std::vector<uint32_t> pjobs;
+  for (size_t j = 0; j < njobs; ++j) {
+    JobDev& J = L->jobs[j];
+    const bool pj = pipelined && J.log2n >= 12;
+    if (pj) {
+      J.logc = 12;
+      J.logr = J.log2n - 12;
+      pjobs.push_back((uint32_t)j);
+    } else {
+      const PassPlan p = plan_for(OP_POLYMUL, J.log2n);
+      J.logc = p.logc;
+      J.logr = p.logr;
+    }
+    if (J.logr > 0 && J.nops == 2) {
       ws_job[j] = ws;
-      ws += (size_t)N * in.count * sizeof(uint64_t);
+      ws += ((size_t)J.count << J.log2n) * sizeof(uint64_t);
     }
   }
-  // work items, in job order within each pass
+  // work items, in job order within each map; every phase's first item is
+  // recorded (also when the job has none in that phase)
   for (size_t j = 0; j < njobs; ++j) {
     JobDev& J = L->jobs[j];
     const uint32_t R = 1u << J.logr;
-    auto add = [&](int g, uint64_t n) -> bool {
+    const bool pj = pipelined && J.log2n >= 12;
+    auto add = [&](int g, int phase, uint64_t n) -> bool {
       if (L->map[g].size() + n > 0x7fffffffull) return false;
-      J.first[g == G_COLF ? PH_COLF : (g == G_COLI ? PH_COLI : PH_ROW)] = (uint32_t)L->map[g].size();
+      J.first[phase] = (uint32_t)L->map[g].size();
       L->map[g].insert(L->map[g].end(), n, (uint32_t)j);
       return true;
     };
     bool ok = true;
-    if (R > 1) {
-      const uint64_t cbs = 1ull << (J.logc - 8);
-      ok = ok && add(G_COLF, (uint64_t)J.nops * J.count * cbs) && add(G_COLI, (uint64_t)J.count * cbs);
+    if (pj) {
+      const uint64_t cols = R > 1 ? 16ull * J.count : 0;
+      ok = add(G_PROW, PH_ROW, (uint64_t)J.count * R) && add(G_PCOLF, PH_COLF, cols * J.nops) &&
+           add(G_PCOLI, PH_COLI, cols);
+    } else {
+      if (R > 1) {
+        const uint64_t cbs = 1ull << (J.logc - 8);
+        ok = add(G_COLF, PH_COLF, (uint64_t)J.nops * J.count * cbs) && add(G_COLI, PH_COLI, (uint64_t)J.count * cbs);
+      }
+      const int g = J.logc <= 12 ? G_ROW12 : (J.logc == 13 ? G_ROW13 : G_ROW14);
+      const uint64_t rows_per_item = J.logc <= 12 ? (4096u >> J.logc) : 1;   // RowGeom<logc>::ROWS
+      const uint64_t tasks = (uint64_t)J.count * R;
+      ok = ok && add(g, PH_ROW, (tasks + rows_per_item - 1) / rows_per_item);
     }
-    const int g = J.logc <= 12 ? G_ROW12 : (J.logc == 13 ? G_ROW13 : G_ROW14);
-    const uint64_t rows_per_item = J.logc <= 12 ? (4096u >> J.logc) : 1;   // RowGeom<logc>::ROWS
-    const uint64_t tasks = (uint64_t)J.count * R;
-    ok = ok && add(g, (tasks + rows_per_item - 1) / rows_per_item);
     if (!ok) return set_error(PM_EINVAL, "batch has more than 2^31 work items in one pass");
+  }
+  if (pipelined) {
+    uint32_t G = set > 1 ? (uint32_t)std::min<int>(set, (int)JOBS_PIPE_MAX_CHUNKS)
+                         : (uint32_t)std::min<uint64_t>(JOBS_PIPE_MAX_AUTO,
+                                                        std::max<uint64_t>(2, pipe_rows / JOBS_PIPE_ROWS_PER_CHUNK));
+    while (!plan_pipeline(L, pjobs, G)) {
+      if (G >= (1u << 20)) return set_error(PM_EINVAL, "batch too large for the pipelined launches");
+      G *= 2;
+    }
   }
   size_t off = align_up(njobs * sizeof(JobDev), 256);
   for (int g = 0; g < NGROUP; ++g) {
@@ -132,9 +242,9 @@ hipError_t launch_all(const Layout& L, char* dev_base, hipStream_t s, bool timed
   const JobDev* jobs = (const JobDev*)dev_base;
   auto map = [&](int g) { return (const uint32_t*)(dev_base + L.off_map[g]); };
   struct Step { int group, phase, maxlogc; const char* name; };
-  static const Step steps[NGROUP] = {{G_COLF, PH_COLF, 0, "jobs_col_fwd"}, {G_ROW12, PH_ROW, 12, "jobs_row_mul_c12"},
-                                     {G_ROW13, PH_ROW, 13, "jobs_row_mul_c13"}, {G_ROW14, PH_ROW, 14, "jobs_row_mul_c14"},
-                                     {G_COLI, PH_COLI, 0, "jobs_col_inv"}};
+  static const Step steps[5] = {{G_COLF, PH_COLF, 0, "jobs_col_fwd"}, {G_ROW12, PH_ROW, 12, "jobs_row_mul_c12"},
+                                {G_ROW13, PH_ROW, 13, "jobs_row_mul_c13"}, {G_ROW14, PH_ROW, 14, "jobs_row_mul_c14"},
+                                {G_COLI, PH_COLI, 0, "jobs_col_inv"}};
   for (const Step& st : steps) {
     const uint32_t n = (uint32_t)L.map[st.group].size();
     if (n == 0) continue;
@@ -144,6 +254,16 @@ hipError_t launch_all(const Layout& L, char* dev_base, hipStream_t s, bool timed
       e = launch_jobs(st.phase, st.maxlogc, L.kind, jobs, map(st.group), n, s);
     } else {
       e = launch_jobs(st.phase, st.maxlogc, L.kind, jobs, map(st.group), n, s);
+    }
+    if (e != hipSuccess) return e;
+  }
+  for (const JobsPipeLaunch& pl : L.pipe) {
+    hipError_t e;
+    if (timed) {
+      ProfScope ps(s, "jobs_pipe_mul_c12");
+      e = launch_jobs_pipe(L.kind, jobs, map(G_PROW), map(G_PCOLF), map(G_PCOLI), pl, s);
+    } else {
+      e = launch_jobs_pipe(L.kind, jobs, map(G_PROW), map(G_PCOLF), map(G_PCOLI), pl, s);
     }
     if (e != hipSuccess) return e;
   }
@@ -310,5 +430,12 @@ int pm_plan_destroy(pm_plan* p) {
 }
 
 size_t pm_plan_device_bytes(const pm_plan* p) { return p ? p->dev_bytes : 0; }
+
+int pm_tune_set_jobs_pipeline(int chunks) {
+  g_jobs_pipe.store(chunks < 0 ? -1 : chunks);
+  return PM_OK;
+}
+
+int pm_tune_get_jobs_pipeline(void) { return g_jobs_pipe.load(); }
 
 }  // extern "C"

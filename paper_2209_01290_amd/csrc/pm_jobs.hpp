@@ -2,6 +2,8 @@
 // device record per job (a group of polynomial pairs sharing N and q), plus
 // per-phase maps from work item to job.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include "modarith.hpp"
 
 namespace pm {
@@ -20,5 +22,15 @@ struct JobDev {
   uint32_t nops, pad;      // operands of the forward column pass (1 or 2)
   uint32_t first[4];       // first work item of the job in each phase's numbering
 };
+
+// One launch of the software-pipelined job table (k_jobs_pipe): nr row work
+// items from r0 of the row map, then nf forward-column items from f0 and ni
+// inverse-column items from i0 of the column maps.
+struct JobsPipeLaunch {
+  uint32_t r0, nr, f0, nf, i0, ni;
+};
+
+hipError_t launch_jobs_pipe(int kind, const JobDev* jobs, const uint32_t* map_row, const uint32_t* map_colf,
+                            const uint32_t* map_coli, const JobsPipeLaunch& L, hipStream_t s);
 
 }  // namespace pm

@@ -16,9 +16,10 @@
 namespace pm {
 
 // ---------------------------------------------------------------- mulmod --
+// c may alias a or b (each word is read and written by the same thread), so
+// no pointer is marked __restrict__.
 template <int KIND>
-__global__ void __launch_bounds__(256) k_mulmod(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
-                                                uint64_t* __restrict__ c, size_t n, Mod M) {
+__global__ void __launch_bounds__(256) k_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t n, Mod M) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) c[i] = mulmod<KIND>(a[i], b[i], M);

@@ -82,6 +82,8 @@ def load():
             "pm_tune_get_small_limit": (sz, [i32, ctypes.c_uint]),
             "pm_tune_set_pipeline": (i32, [i32]),
             "pm_tune_get_pipeline": (i32, []),
+            "pm_tune_set_jobs_pipeline": (i32, [i32]),
+            "pm_tune_get_jobs_pipeline": (i32, []),
             "pm_ntt_primes": (sz, [u64, ctypes.c_uint, sz, u64p]),
             "pm_find_psi": (u64, [u64, sz]),
             "pm_make_tables": (i32, [u64, sz, u64, u64p, u64p]),
@@ -129,7 +131,9 @@ def exported_symbols():
             "pm_make_tables_u32", "pm_ntt_fwd_il", "pm_ntt_inv_il", "pm_polymul_il",
             "pm_polymul_il_workspace_bytes", "pm_tune_set_small", "pm_tune_get_small",
             "pm_tune_set_small_batch", "pm_tune_get_small_batch", "pm_tune_set_small_limit",
-            "pm_tune_get_small_limit", "pm_tune_set_pipeline", "pm_tune_get_pipeline"]
+            "pm_tune_get_small_limit", "pm_tune_set_pipeline", "pm_tune_get_pipeline",
+            "pm_tune_set_jobs_pipeline",
+            "pm_tune_get_jobs_pipeline"]
 
 
 def _check(rc: int, func: str):
@@ -416,6 +420,15 @@ def pm_tune_set_pipeline(chunks):
     """Limb chunks of the software-pipelined product: -1 = built-in choice,
     0 or 1 = off, G >= 2 = G chunks."""
     _check(load().pm_tune_set_pipeline(int(chunks)), "pm_tune_set_pipeline")
+
+
+def pm_tune_set_jobs_pipeline(chunks):
+    """Chunks of the software-pipelined job tables: -1 automatic, 0 off, G >= 2 forced."""
+    _check(load().pm_tune_set_jobs_pipeline(int(chunks)), "pm_tune_set_jobs_pipeline")
+
+
+def pm_tune_get_jobs_pipeline():
+    return int(load().pm_tune_get_jobs_pipeline())
 
 
 def pm_tune_get_pipeline():

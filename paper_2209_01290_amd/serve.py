@@ -5,19 +5,24 @@ largest 60-bit prime q = 1 mod 2N), i.e. L jobs of one pair each. Requests
 arrive on a clock (a seeded Poisson trace); the loop
 
   * queues arrivals in FIFO order;
-  * admits the head of the queue while its HBM footprint (output words plus
-    the column-pass intermediate) fits the free part of a device arena, so
-    requests that arrive while others run are admitted as memory frees up;
-  * forms a batch of every newly admitted request -- any mix of N -- and
-    launches it as one pm_polymul_jobs call (one launch per pass for the
-    whole mix) on the next of S streams, so up to S batches overlap on the
-    device;
-  * polls the batches' completion events, records each request's latency
-    (completion seen on the host minus arrival) and frees its memory.
+  * admits requests from the head of the queue while their HBM footprint
+    fits the free part of a device arena: 24 N L bytes each (operands a and b,
+    output c) plus the batch's workspace (the column-pass copy of b and the
+    job table), so requests that arrive while others run are admitted as
+    memory frees up;
+  * forms a batch of every newly admitted request -- any mix of N -- in one
+    arena block, copies each request's operands into its slots there (on
+    the batch's stream, ahead of the product), and launches the batch as one
+    pm_polymul_jobs call on the next free of S streams (a batch of one
+    request as one pm_polymul), so up to S batches overlap on the device;
+  * polls the completion event of every batch in flight (batches on
+    different streams finish in any order), records each finished request's
+    latency (completion seen on the host minus arrival) and frees its block.
 
-Operands stay resident on the device: per N, a pool of operand sets (60 limbs
-each) drawn once with the device generator; request r uses pool entry
-r mod pool_size. Twiddle tables for every (N, limb) are resident as well.
+Operand sources stay resident on the device: per N, a pool of operand sets
+(60 limbs each) drawn once with the device generator; request r's operands
+are copied from pool entry r mod pool_size (this copy stands for the request
+bringing its operands). Twiddle tables for every (N, limb) are resident.
 
 The scheduling logic is independent of the device: `Engine` drives an
 executor object; `GpuExecutor` runs the library, tests on the CPU use a fake.
@@ -67,6 +72,9 @@ class Arena:
                 return off, n
         return None
 
+    def largest_free(self) -> int:
+        return max((ln for _, ln in self.free), default=0)
+
     def release(self, off: int, n: int):
         self.used -= n
         i = 0
@@ -83,30 +91,40 @@ class Arena:
 
 
 class Request:
-    __slots__ = ("rid", "arrival", "log2n", "limbs", "t_admit", "t_done", "alloc", "state")
+    __slots__ = ("rid", "arrival", "log2n", "limbs", "t_admit", "t_done", "slot", "state")
 
     def __init__(self, rid, arrival, log2n, limbs):
         self.rid, self.arrival, self.log2n, self.limbs = rid, arrival, log2n, limbs
         self.t_admit = self.t_done = None
-        self.alloc = None
+        self.slot = None                # arena byte offset of its operand a (then b, then c)
         self.state = "pending"
 
 
+def _align(n: int) -> int:
+    return (n + ALIGN - 1) // ALIGN * ALIGN
+
+
 def footprint(log2n: int, limbs: int) -> int:
-    """Arena bytes a request holds while admitted: its output words."""
-    return (1 << log2n) * limbs * 8
+    """HBM bytes of a request's words: operands a and b and output c, 24 N L."""
+    return 24 * (1 << log2n) * limbs
 
 
-def batch_workspace(log2n: int, limbs: int) -> int:
+def request_workspace(log2n: int, limbs: int) -> int:
     """Upper bound of the workspace bytes a request adds to its batch: the
     column-pass copy of b when the product runs in two passes, plus its
-    job-table entries (one 120-byte record and at most 80 work-item slots of
-    4 bytes per limb). A batch also needs BATCH_WS_SLACK for alignment."""
+    job-table entries (one record of at most 256 bytes and at most 80
+    work-item slots of 4 bytes per limb)."""
     N = 1 << log2n
-    return (N * limbs * 8 if log2n > 12 else 0) + limbs * 512
+    return (N * limbs * 8 if log2n > 12 else 0) + limbs * 576
 
 
-BATCH_WS_SLACK = 8192
+def request_bytes(log2n: int, limbs: int) -> int:
+    """Arena bytes a request takes in its batch's block: its footprint and its
+    share of the batch workspace, each 256-byte aligned."""
+    return _align(footprint(log2n, limbs)) + _align(request_workspace(log2n, limbs))
+
+
+BATCH_WS_SLACK = 8192     # per batch: alignment of the workspace parts
 
 
 class Engine:
@@ -117,12 +135,11 @@ class Engine:
     device completes and is counted as a late cancellation."""
 
     def __init__(self, executor, budget_bytes: int, streams: int = 3, max_batch_products: int = 4096,
-                 batch_ws_bytes: int | None = None, deadline_s: float | None = None):
+                 deadline_s: float | None = None):
         self.ex = executor
         self.arena = Arena(budget_bytes)
         self.streams = streams
         self.max_batch_products = max_batch_products
-        self.batch_ws = batch_ws_bytes if batch_ws_bytes is not None else executor.batch_workspace_bytes()
         self.deadline_s = deadline_s
 
     def run(self, trace, time_scale: float = 1.0, on_complete=None, cancels=None):
@@ -140,7 +157,7 @@ class Engine:
     def _run(self, trace, time_scale, on_complete, cancels):
         reqs = [Request(i, t * time_scale, n, L) for i, (t, n, L) in enumerate(trace)]
         queue = collections.deque()
-        inflight = collections.deque()          # (handle, [requests], unused)
+        inflight = []                           # (handle, [requests], arena block)
         max_inflight = 0
         rejected = []                           # rejected at arrival, timed out or cancelled
         late_cancel = 0
@@ -160,8 +177,7 @@ class Engine:
                     r.state = "cancelled"
                     r.t_done = now
                     rejected.append(r)
-                elif footprint(r.log2n, r.limbs) > self.arena.size or \
-                        batch_workspace(r.log2n, r.limbs) > self.batch_ws - BATCH_WS_SLACK:
+                elif request_bytes(r.log2n, r.limbs) + BATCH_WS_SLACK > self.arena.size:
                     r.state = "rejected"
                     rejected.append(r)
                 else:
@@ -192,37 +208,45 @@ class Engine:
                 queue = kept
                 drop_now.clear()
             max_queue = max(max_queue, len(queue))
-            # completions
-            while inflight and self.ex.done(inflight[0][0]):
-                handle, batch, _ = inflight.popleft()
-                tdone = time.monotonic() - t0
-                for r in batch:
-                    r.t_done = tdone
-                    r.state = "done"
-                    if on_complete is not None:
-                        on_complete(r, self.ex)
-                    self.arena.release(*r.alloc)
-                    done += 1
-                self.ex.finish(handle)
-            # admission and launch
+            # completions: every batch in flight is polled, so a batch that
+            # finishes before an earlier one is recorded and freed at once
+            if inflight:
+                still = []
+                for ent in inflight:
+                    handle, batch, block = ent
+                    if not self.ex.done(handle):
+                        still.append(ent)
+                        continue
+                    tdone = time.monotonic() - t0
+                    for r in batch:
+                        r.t_done = tdone
+                        r.state = "done"
+                        if on_complete is not None:
+                            on_complete(r, self.ex)
+                        done += 1
+                    self.arena.release(*block)
+                    self.ex.finish(handle)
+                inflight = still
+            # admission and launch: requests from the head of the queue while
+            # the batch's block (footprints and workspace) fits the arena
             if queue and len(inflight) < self.streams:
-                batch, products, wsb = [], 0, 0
+                batch, products, need = [], 0, BATCH_WS_SLACK
+                room = self.arena.largest_free()
                 while queue and products + queue[0].limbs <= self.max_batch_products:
                     r = queue[0]
-                    need = batch_workspace(r.log2n, r.limbs)
-                    if wsb + need > self.batch_ws - BATCH_WS_SLACK:
-                        break
-                    a = self.arena.alloc(footprint(r.log2n, r.limbs))
-                    if a is None:
+                    add = request_bytes(r.log2n, r.limbs)
+                    if need + add > room:
                         break
                     queue.popleft()
-                    r.alloc, r.t_admit, r.state = a, now, "admitted"
+                    r.t_admit, r.state = now, "admitted"
                     batch.append(r)
                     products += r.limbs
-                    wsb += need
+                    need += add
                 if batch:
-                    handle = self.ex.launch(batch, batches)
-                    inflight.append((handle, batch, None))
+                    block = self.arena.alloc(need)
+                    assert block is not None, "arena block smaller than its largest free extent"
+                    handle = self.ex.launch(batch, batches, block)
+                    inflight.append((handle, batch, block))
                     max_inflight = max(max_inflight, len(inflight))
                     batches += 1
                     batch_sizes.append(len(batch))
@@ -260,16 +284,20 @@ class Engine:
 
 
 class GpuExecutor:
-    """Runs batches with pm_polymul_jobs: outputs in a device arena, one fixed
-    workspace per stream, operand pools and tables resident. A batch of one
-    request (the common case below saturation) runs as one pm_polymul over
-    its limbs instead (single_request_path): its operands, tables and arena
-    slot are contiguous [limbs][N] blocks, and pm_polymul takes the tuned
-    small-batch plan when the request is small enough to be latency-bound."""
+    """Runs batches with pm_polymul_jobs in blocks of one device arena, with
+    operand pools and tables resident. In a batch's block each request has
+    three [limbs][N] slots (a, b, c) and the batch's workspace follows them;
+    the request's operands are copied into its slots on the batch's stream
+    before the product. A batch of one request (the common case below
+    saturation) runs as one pm_polymul over its limbs instead
+    (single_request_path): its slots and tables are contiguous [limbs][N]
+    blocks, and pm_polymul takes the tuned small-batch plan when the request
+    is small enough to be latency-bound. Each batch runs on a stream that no
+    batch in flight is using."""
 
     def __init__(self, budget_bytes: int, streams: int = 3, pool: int = 4, max_limbs: int = 60,
                  log2ns=workloads.SERVE_LOG2N, device="cuda", seed: int = SEED,
-                 ws_bytes_per_stream: int = 2 << 30, single_request_path: bool = True):
+                 single_request_path: bool = True):
         import torch
         from . import lib, synth
         self.torch, self.lib = torch, lib
@@ -278,8 +306,7 @@ class GpuExecutor:
         self.arena_t = torch.empty(budget_bytes // 8, dtype=torch.int64, device=self.dev)
         self.base = self.arena_t.data_ptr()
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(streams)]
-        self.ws = [torch.empty(ws_bytes_per_stream // 8, dtype=torch.int64, device=self.dev) for _ in range(streams)]
-        self.ws_bytes = ws_bytes_per_stream
+        self.busy = [False] * streams
         self.pool = pool
         self.max_limbs = max_limbs
         self.tables = workloads.Tables(self.dev)
@@ -296,25 +323,21 @@ class GpuExecutor:
                 synth.uniform_mod_device([synth.key(seed, p, l, 0, 1) for l in range(max_limbs)], N,
                                          prm.q[:max_limbs], b[p])
             self.inputs[log2n] = (a, b)
-        # job records per (N, pool entry) for all max_limbs limbs, output
-        # pointers aside: a request takes the first L rows and sets its outputs
-        self.rows, self.c_off = {}, {}
+        # job records per N for all max_limbs limbs (moduli and tables),
+        # operand and output pointers aside: a request takes the first L rows
+        self.rows, self.l_off = {}, {}
         for log2n in log2ns:
             N = 1 << log2n
             prm = self.tables.get(log2n, max_limbs)
-            a, b = self.inputs[log2n]
             lidx = np.arange(max_limbs, dtype=np.uint64) * np.uint64(N * 8)
-            self.c_off[log2n] = lidx
-            for p in range(pool):
-                rows = np.zeros(max_limbs, dtype=JOB_DTYPE)
-                rows["log2n"] = log2n
-                rows["count"] = 1
-                rows["q"] = np.array(prm.q[:max_limbs], dtype=np.uint64)
-                rows["psi_br"] = np.uint64(prm.psi_br.data_ptr()) + lidx
-                rows["psi_inv_br"] = np.uint64(prm.psi_inv_br.data_ptr()) + lidx
-                rows["a"] = np.uint64(a[p].data_ptr()) + lidx
-                rows["b"] = np.uint64(b[p].data_ptr()) + lidx
-                self.rows[(log2n, p)] = rows
+            self.l_off[log2n] = lidx
+            rows = np.zeros(max_limbs, dtype=JOB_DTYPE)
+            rows["log2n"] = log2n
+            rows["count"] = 1
+            rows["q"] = np.array(prm.q[:max_limbs], dtype=np.uint64)
+            rows["psi_br"] = np.uint64(prm.psi_br.data_ptr()) + lidx
+            rows["psi_inv_br"] = np.uint64(prm.psi_inv_br.data_ptr()) + lidx
+            self.rows[log2n] = rows
         self.single_request_path = single_request_path
         self.qarr = {n: (ctypes.c_uint64 * max_limbs)(*self.tables.get(n, max_limbs).q[:max_limbs])
                      for n in log2ns}
@@ -323,55 +346,76 @@ class GpuExecutor:
     def budget(self):
         return self.arena_t.numel() * 8
 
-    def batch_workspace_bytes(self):
-        return self.ws_bytes
-
     def resident_bytes(self):
         t = sum(2 * x[0].numel() * 8 for x in self.inputs.values())
         t += sum(2 * p.psi_br.numel() * 8 for p in self.tables.by_n.values())
-        return t + self.budget() + len(self.ws) * self.ws_bytes
+        return t + self.budget()
 
-    def job_rows(self, r, out_ptr=None):
-        """pm_job records of request r (output in its arena slot, or at out_ptr)."""
-        rows = self.rows[(r.log2n, r.rid % self.pool)][:r.limbs].copy()
-        base = out_ptr if out_ptr is not None else self.base + r.alloc[0]
-        rows["c"] = np.uint64(base) + self.c_off[r.log2n][:r.limbs]
+    def job_rows(self, r, a_ptr, b_ptr, c_ptr):
+        """pm_job records of request r with its operands and output at the given addresses."""
+        rows = self.rows[r.log2n][:r.limbs].copy()
+        off = self.l_off[r.log2n][:r.limbs]
+        rows["a"] = np.uint64(a_ptr) + off
+        rows["b"] = np.uint64(b_ptr) + off
+        rows["c"] = np.uint64(c_ptr) + off
         return rows
 
-    def inputs_of(self, r):
+    def pool_operands(self, r):
+        """(a, b) of request r in its operand pool entry: [limbs, N] views."""
         a, b = self.inputs[r.log2n]
         p = r.rid % self.pool
         return a[p, :r.limbs], b[p, :r.limbs]
 
-    def output(self, r):
+    def _slot(self, byte_off, r):
         N = 1 << r.log2n
-        off = r.alloc[0] // 8
-        return self.arena_t[off: off + r.limbs * N].view(r.limbs, N)
+        w = byte_off // 8
+        return self.arena_t[w: w + r.limbs * N].view(r.limbs, N)
 
-    def launch(self, batch, k):
-        i = k % len(self.streams)
-        s, ws = self.streams[i], self.ws[i]
+    def slots(self, r):
+        """The device views (a, b, c) of request r's slots in its batch's block."""
+        nb = 8 * (1 << r.log2n) * r.limbs
+        return self._slot(r.slot, r), self._slot(r.slot + nb, r), self._slot(r.slot + 2 * nb, r)
+
+    def output(self, r):
+        return self.slots(r)[2]
+
+    def launch(self, batch, k, block):
+        i = self.busy.index(False)          # the engine keeps at most len(streams) batches in flight
+        self.busy[i] = True
+        s = self.streams[i]
+        off = block[0]
+        for r in batch:
+            r.slot = off
+            off += _align(footprint(r.log2n, r.limbs))
+        ws_off = _align(off)
+        ws_bytes = block[0] + block[1] - ws_off
+        with self.torch.cuda.stream(s):
+            for r in batch:
+                a_src, b_src = self.pool_operands(r)
+                a_dst, b_dst, _ = self.slots(r)
+                a_dst.copy_(a_src, non_blocking=True)
+                b_dst.copy_(b_src, non_blocking=True)
         if len(batch) == 1 and self.single_request_path:
             r = batch[0]
-            a, b = self.inputs[r.log2n]
-            p = r.rid % self.pool
+            a, b, c = self.slots(r)
             prm = self.tables.get(r.log2n, self.max_limbs)
-            self.lib.pm_polymul_raw(a[p].data_ptr(), b[p].data_ptr(), self.base + r.alloc[0], 1 << r.log2n,
-                                    r.limbs, 1, self.qarr[r.log2n], prm.psi_br.data_ptr(),
-                                    prm.psi_inv_br.data_ptr(), ws.data_ptr(), s.cuda_stream)
+            self.lib.pm_polymul_raw(a.data_ptr(), b.data_ptr(), c.data_ptr(), 1 << r.log2n, r.limbs, 1,
+                                    self.qarr[r.log2n], prm.psi_br.data_ptr(), prm.psi_inv_br.data_ptr(),
+                                    self.base + ws_off, s.cuda_stream)
         else:
-            jobs = np.concatenate([self.job_rows(r) for r in batch])
-            self.lib.pm_polymul_jobs_raw(jobs.ctypes.data, len(jobs), ws.data_ptr(), self.ws_bytes,
-                                         s.cuda_stream)
+            jobs = np.concatenate([self.job_rows(r, *(t.data_ptr() for t in self.slots(r))) for r in batch])
+            self.lib.pm_polymul_jobs_raw(jobs.ctypes.data, len(jobs), self.base + ws_off, ws_bytes, s.cuda_stream)
         ev = self.torch.cuda.Event()
         ev.record(s)
-        return (ev, s)
+        return (ev, i)
 
     def run_alone(self, r):
-        """Request r on its own (same entry point), into a fresh output tensor."""
+        """Request r on its own through pm_polymul_jobs, reading its operands
+        in the pool, into a fresh output tensor."""
         torch = self.torch
         out = torch.empty((r.limbs, 1 << r.log2n), dtype=torch.int64, device=self.dev)
-        jobs = self.job_rows(r, out_ptr=out.data_ptr())
+        a, b = self.pool_operands(r)
+        jobs = self.job_rows(r, a.data_ptr(), b.data_ptr(), out.data_ptr())
         need = self.lib.pm_polymul_jobs_workspace_bytes_raw(jobs.ctypes.data, len(jobs))
         ws = torch.empty(max(need // 8 + 64, 64), dtype=torch.int64, device=self.dev)
         self.lib.pm_polymul_jobs_raw(jobs.ctypes.data, len(jobs), ws.data_ptr(), ws.numel() * 8,
@@ -383,7 +427,7 @@ class GpuExecutor:
         return handle[0].query()
 
     def finish(self, handle):
-        pass
+        self.busy[handle[1]] = False
 
 
 def warm_up(ex):
@@ -395,9 +439,8 @@ def warm_up(ex):
 
 
 def run_rates(rates, nreq, budget_gib=32.0, streams=3, seed=SEED, verbose=True, ex=None,
-              max_batch_products=4096, ws_gib=2.0):
-    ex = ex or GpuExecutor(int(budget_gib * (1 << 30)), streams=streams, seed=seed,
-                           ws_bytes_per_stream=int(ws_gib * (1 << 30)))
+              max_batch_products=4096):
+    ex = ex or GpuExecutor(int(budget_gib * (1 << 30)), streams=streams, seed=seed)
     warm_up(ex)
     out = []
     for rate in rates:
@@ -419,13 +462,12 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--streams", type=int, default=3)
     ap.add_argument("--max-batch-products", type=int, default=4096, help="limb-products per batch at most")
-    ap.add_argument("--ws-gib", type=float, default=2.0, help="batch workspace per stream (GiB)")
     a = ap.parse_args()
     from . import lib
     lib.load()
     lib.apply_tune_db()
     run_rates([float(x) for x in a.rates.split(",")], a.requests, a.budget_gib, a.streams,
-              max_batch_products=a.max_batch_products, ws_gib=a.ws_gib)
+              max_batch_products=a.max_batch_products)
 
 
 if __name__ == "__main__":

@@ -119,6 +119,10 @@ class MixedBatch:
         log2n, _ = self.slot[(r, l)]
         return self.tables.get(log2n, 0).q[l]
 
+    def modulus_of_limb(self, log2n, l):
+        """Limb l's modulus for size 2^log2n (the l-th largest prime q = 1 mod 2N)."""
+        return self.tables.get(log2n, 0).q[l]
+
     def host_operands(self, r, l):
         """The same (a, b) drawn again on the host."""
         log2n, _ = self.slot[(r, l)]

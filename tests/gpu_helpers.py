@@ -89,4 +89,23 @@ class tuned:
                 L.pm_tune_set_small_limit(op, n, 0)
         L.pm_tune_set_small_batch(0)
         L.pm_tune_set_pipeline(-1)
+        L.pm_tune_set_jobs_pipeline(-1)
         return False
+
+
+def host_threads():
+    """Worker threads for oracle checks: the CPUs this process may use, at most 16."""
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_parallel(fn, items, threads=None):
+    """[fn(item) for item in items] over a thread pool (the oracle's ctypes
+    calls release the interpreter lock, so the C work runs in parallel)."""
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(threads or host_threads()) as ex:
+        return list(ex.map(fn, items))

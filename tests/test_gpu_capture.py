@@ -1,7 +1,7 @@
 """The library under HIP-graph capture and under concurrent host threads.
 
-Capture: pm_polymul and pm_ntt_fwd (throughput and small-batch plans) are
-captured into one graph; the graph is replayed several times with eager work
+Capture: pm_polymul and pm_ntt_fwd (throughput, small-batch and
+software-pipelined plans) are captured into one graph; the graph is replayed several times with eager work
 and synchronisations between replays, and every replay must reproduce the
 eager results bit for bit (the library records no memset nodes).
 Threads: four host threads issue products on their own streams at once;
@@ -30,10 +30,12 @@ def _eq(got, want, what):
     assert msg is None, "%s: %s" % (what, msg)
 
 
-@pytest.mark.parametrize("small", [False, True], ids=["throughput", "small"])
+@pytest.mark.parametrize("small", [False, True, "pipelined"], ids=["throughput", "small", "pipelined"])
 @pytest.mark.parametrize("log2n", [10, 14, 16])
 def test_graph_capture_replays(L, log2n, small):
     import torch
+    if small == "pipelined":
+        log2n = {10: 15, 14: 16, 16: 17}[log2n]     # the pipelined plan needs N = 2^15..2^17
     N, limbs, polys = 1 << log2n, 2, 2
     qs = L.pm_ntt_primes(N, limbs)
     prm = L.Params(N, limbs, primes=qs)
@@ -42,7 +44,9 @@ def test_graph_capture_replays(L, log2n, small):
     want_mul = oracle_polymul(a, b, qs, N, fw_o, iv_o)
     want_fwd = oracle_ntt_fwd(a, qs, fw_o)
     try:
-        if small:
+        if small == "pipelined":
+            L.pm_tune_set_pipeline(2)
+        elif small:
             for op in (L.OP_NTT_FWD, L.OP_POLYMUL):
                 L.pm_tune_set_small(op, log2n, min(log2n, 11) if log2n > 12 else log2n, 4)
             L.pm_tune_set_small_batch(1 << 22)
@@ -79,7 +83,19 @@ def test_graph_capture_replays(L, log2n, small):
             L.pm_ntt_fwd(x, N, limbs, polys, qs, prm.psi_br)
             torch.cuda.synchronize()
         del g
+        if small == "pipelined":           # the captured launches were the pipelined ones
+            counts = {}
+            L.pm_prof_enable(True)
+            try:
+                L.pm_prof_read()
+                L.pm_polymul(da, db, dc, N, limbs, polys, qs, prm.psi_br, prm.psi_inv_br, ws)
+                torch.cuda.synchronize()
+                counts = {k: n for k, (n, _ms) in L.pm_prof_read().items()}
+            finally:
+                L.pm_prof_enable(False)
+            assert counts.get("pipe_mul_c12", 0) == 4, counts
     finally:
+        L.pm_tune_set_pipeline(-1)
         for op in (L.OP_NTT_FWD, L.OP_POLYMUL):
             L.pm_tune_set_small(op, log2n, 0, 0)
         L.pm_tune_set_small_batch(0)

@@ -1,6 +1,10 @@
 """Batched job tables (pm_polymul_jobs, pm_plan_*): mixed N, moduli and
 aliasing in one batch, checked word for word against the oracle; graph
-replays checked one by one with eager work in between."""
+replays checked one by one with eager work in between. Both forms: three
+launches (one per pass of Eq. 2) and the software-pipelined launches (rows of
+2^12 words of one chunk of products beside the column passes of its
+neighbours), with chunk boundaries inside jobs, empty chunks, and the
+automatic choice at a batch above the pipelining threshold."""
 import numpy as np
 import pytest
 
@@ -16,7 +20,8 @@ def L():
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     from paper_2209_01290_amd import lib
     lib.load()
-    return lib
+    yield lib
+    lib.pm_tune_set_jobs_pipeline(-1)
 
 
 # (log2n, count, bits of the prime search, prime index, alias)
@@ -133,3 +138,110 @@ def test_jobs_validation(L):
     ws = torch.empty(16, dtype=torch.int64, device="cuda")
     with pytest.raises(L.PMError):
         L.pm_polymul_jobs(jobs + [bad], ws)
+
+
+def _launch_counts(L, fn):
+    import torch
+    L.pm_prof_enable(True)
+    try:
+        L.pm_prof_read()
+        fn()
+        torch.cuda.synchronize()
+        return {name: n for name, (n, _ms) in L.pm_prof_read().items()}
+    finally:
+        L.pm_prof_enable(False)
+
+
+# chunk counts: boundaries inside jobs of several products (2, 3, 7) and more
+# chunks than pipelined products (40: empty chunks are skipped)
+@pytest.mark.parametrize("chunks", [2, 3, 7, 40])
+def test_jobs_pipelined(L, chunks):
+    import torch
+    jobs, keep, want = _build(L, MIX, request0=200 + chunks)
+    L.pm_tune_set_jobs_pipeline(chunks)
+    try:
+        nbytes = L.pm_polymul_jobs_workspace_bytes(jobs)
+        ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device="cuda")
+        counts = _launch_counts(L, lambda: L.pm_polymul_jobs(jobs, ws))
+    finally:
+        L.pm_tune_set_jobs_pipeline(-1)
+    _check_all(L, keep, want, "pipelined G=%d" % chunks)
+    # the jobs of N >= 2^12 ran in pipelined launches (at most G + 2), the
+    # smaller ones in one three-pass row launch before them
+    assert 1 <= counts.get("jobs_pipe_mul_c12", 0) <= chunks + 2, counts
+    assert counts.get("jobs_row_mul_c12", 0) == 1 and "jobs_col_fwd" not in counts, counts
+
+
+def test_plan_replays_pipelined(L):
+    """The pipelined launches captured in a plan's graph, replayed with eager
+    work in between; every replay checked."""
+    import torch
+    jobs, keep, want = _build(L, MIX, request0=300)
+    L.pm_tune_set_jobs_pipeline(3)
+    try:
+        plan = L.pm_plan_create(jobs)
+    finally:
+        L.pm_tune_set_jobs_pipeline(-1)
+    try:
+        for rep in range(3):
+            for k in keep:
+                k[2].copy_(L.to_device(k[5][0]))
+                if k[3].data_ptr() != k[2].data_ptr():
+                    k[3].copy_(L.to_device(k[6][0]))
+            x = L.to_device(np.arange(1, 1025, dtype=np.uint64))
+            L.pm_barrett_mulmod(x, x, x, 12289)
+            torch.cuda.synchronize()
+            L.pm_plan_launch(plan)
+            torch.cuda.synchronize()
+            _check_all(L, keep, want, "pipelined replay %d" % rep)
+    finally:
+        L.pm_plan_destroy(plan)
+
+
+def test_jobs_pipelined_automatic_at_threshold(L):
+    """Above 2048 rows of 2^12 words the default pipelines the table: the
+    result equals the three-pass form word for word, and the oracle on
+    sampled products of every job."""
+    import torch
+    from gpu_helpers import oracle_tables as ot
+    import oracle
+    # 40 x 2^16 (640 rows) + 44 x 2^17 (1408 rows) = 2048 rows, 4 jobs with chunk boundaries inside them
+    spec = [(16, 25, 0), (17, 20, 1), (16, 15, 2), (17, 24, 3)]
+    jobs, keep = [], []
+    for i, (log2n, count, qi) in enumerate(spec):
+        N = 1 << log2n
+        q = L.pm_ntt_primes(N, qi + 1)[qi]
+        a, b = synth.operands(synth.SEED_BASE + 6, [q], count, N, request=i)
+        fw, iv = L.pm_make_tables(q, N)
+        dfw, div = L.to_device(fw), L.to_device(iv)
+        da, db = L.to_device(a[0]), L.to_device(b[0])
+        dc = torch.empty_like(da)
+        jobs.append(L.make_job(log2n, count, q, dfw, div, da, db, dc))
+        keep.append((dfw, div, da, db, dc, a, b, q))
+    nbytes = max(L.pm_polymul_jobs_workspace_bytes(jobs), 8)
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device="cuda")
+    L.pm_tune_set_jobs_pipeline(-1)
+    counts = _launch_counts(L, lambda: L.pm_polymul_jobs(jobs, ws))
+    assert counts.get("jobs_pipe_mul_c12", 0) == 4, counts          # G = 2: four launches
+    piped = [L.to_host(k[4]).copy() for k in keep]
+    for k in keep:
+        k[4].zero_()
+    L.pm_tune_set_jobs_pipeline(0)
+    try:
+        nbytes = max(L.pm_polymul_jobs_workspace_bytes(jobs), 8)
+        ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device="cuda")
+        counts = _launch_counts(L, lambda: L.pm_polymul_jobs(jobs, ws))
+    finally:
+        L.pm_tune_set_jobs_pipeline(-1)
+    assert "jobs_pipe_mul_c12" not in counts and counts.get("jobs_col_fwd", 0) == 1, counts
+    o = oracle.default()
+    for i, k in enumerate(keep):
+        three = L.to_host(k[4])
+        assert np.array_equal(three, piped[i]), "job %d: pipelined and three-pass differ" % i
+        log2n, count = spec[i][0], spec[i][1]
+        q, a, b = k[7], k[5], k[6]
+        fw, iv = ot([q], 1 << log2n)
+        for p in (0, count // 2, count - 1):
+            want = o.polymul_ntt(a[0, p], b[0, p], q, fw[0], iv[0])
+            msg = first_mismatch(piped[i].reshape(count, -1)[p], want)
+            assert msg is None, "job %d product %d: %s" % (i, p, msg)

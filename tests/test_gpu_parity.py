@@ -68,6 +68,28 @@ def test_barrett_mulmod(L, q):
     _assert_equal(L.to_host(dc), oracle.default().mulmod_vec(a, b, q), "mulmod q=%d" % q)
 
 
+@pytest.mark.parametrize("alias", ["c=a", "c=b", "a=b=c"])
+def test_barrett_mulmod_aliased(L, alias):
+    """c may alias a or b (pm.h): the in-place products equal the oracle's."""
+    from paper_2209_01290_amd import synth
+    q = (1 << 60) - (1 << 14) + 1
+    n = (1 << 16) + 77
+    a = synth.uniform_mod(synth.key(12, 0), n, q)
+    b = synth.uniform_mod(synth.key(12, 1), n, q)
+    da, db = L.to_device(a), L.to_device(b)
+    if alias == "c=a":
+        L.pm_barrett_mulmod(da, db, da, q)
+        got, want = da, oracle.default().mulmod_vec(a, b, q)
+    elif alias == "c=b":
+        L.pm_barrett_mulmod(da, db, db, q)
+        got, want = db, oracle.default().mulmod_vec(a, b, q)
+    else:
+        L.pm_barrett_mulmod(da, da, da, q)
+        got, want = da, oracle.default().mulmod_vec(a, a, q)
+    _sync()
+    _assert_equal(L.to_host(got), want, "mulmod %s" % alias)
+
+
 def test_barrett_worked_example(L):
     a, b, q = 994674970, 994705408, 994705409
     da, db = L.to_device(np.array([a], np.uint64)), L.to_device(np.array([b], np.uint64))
@@ -351,27 +373,41 @@ def test_config2_stagewise_full_size(L):
 
 def test_config3_full_size(L):
     """N=2^16, 48 limbs x 8 pairs (the benchmark shape) plus the standalone
-    forward NTT of the a operands; oracle on sampled polynomials and
-    coefficients."""
+    forward NTT of the a operands: every one of the 384 products, in the
+    software-pipelined form the benchmark times and in the three-pass form,
+    and every forward transform, word for word against the oracle."""
+    from gpu_helpers import oracle_parallel
     N, limbs, polys = 2**16, 48, 8
     qs = L.pm_ntt_primes(N, limbs)
     _, _, dfw, div = device_tables(qs, N)
     a, b = operands(N, qs, polys, seed=220901290 + 3)
     da, db = L.to_device(a), L.to_device(b)
     dc = torch_empty_like(da)
+    got = {}
     with tuned(L):                       # the plans the benchmark runs
-        L.pm_polymul(da, db, dc, N, limbs, polys, qs, dfw, div, workspace(L, N, limbs, polys))
+        for form, chunks in (("pipelined", -1), ("three-pass", 0)):
+            L.pm_tune_set_pipeline(chunks)
+            dc.zero_()
+            L.pm_polymul(da, db, dc, N, limbs, polys, qs, dfw, div, workspace(L, N, limbs, polys))
+            _sync()
+            got[form] = L.to_host(dc).reshape(a.shape)
         x = da.clone()
         L.pm_ntt_fwd(x, N, limbs, polys, qs, dfw)
         _sync()
-    got = L.to_host(dc).reshape(a.shape)
     fwd = L.to_host(x).reshape(a.shape)
     o = oracle.default()
-    for l, p in [(0, 0), (17, 3), (47, 7)]:
-        fw, iv = o.psi_tables(qs[l], N)
-        _assert_equal(got[l, p], o.polymul_ntt(a[l, p], b[l, p], qs[l], fw, iv), "config 3 (%d,%d)" % (l, p))
-        _assert_equal(fwd[l, p], o.ntt_fwd(a[l, p], qs[l], fw), "config 3 fwd (%d,%d)" % (l, p))
-    rng = np.random.default_rng(3)
-    for _ in range(12):
-        l, p, k = int(rng.integers(limbs)), int(rng.integers(polys)), int(rng.integers(N))
-        assert int(got[l, p, k]) == o.polymul_coeff(a[l, p], b[l, p], qs[l], k), (l, p, k)
+    tables = oracle_parallel(lambda q: o.psi_tables(q, N), qs)
+
+    def check(lp):
+        l, p = lp
+        fw, iv = tables[l]
+        want = o.polymul_ntt(a[l, p], b[l, p], qs[l], fw, iv)
+        bad = [form for form in got if not np.array_equal(got[form][l, p], want)]
+        if not np.array_equal(fwd[l, p], o.ntt_fwd(a[l, p], qs[l], fw)):
+            bad.append("ntt_fwd")
+        return bad
+
+    pairs = [(l, p) for l in range(limbs) for p in range(polys)]
+    res = oracle_parallel(check, pairs)
+    wrong = [(lp, bad) for lp, bad in zip(pairs, res) if bad]
+    assert not wrong, "%d of 384 products differ from the oracle, first: %s" % (len(wrong), wrong[0])

@@ -4,8 +4,10 @@ bit-exact oracle results: no row kernel reads an LDS slot that the current
 exchange did not write (a missing barrier or an indexing error would show up
 as a mismatch). Called through the debug library's own C ABI, for every
 row mode and both row geometries, single- and two-pass splits, the four-word
-column pass from 2^4 to 2^7 rows (odd and even depths), and the
-batched-jobs kernels."""
+column pass from 2^4 to 2^7 rows (odd and even depths), the batched-jobs
+kernels in both forms, and the software-pipelined product (row workgroups
+beside column workgroups in one launch) for Eq. 2, the fused product and
+squaring."""
 import ctypes
 import os
 
@@ -35,6 +37,8 @@ def env():
         getattr(P, name).argtypes = [vp, sz, sz, sz, u64p, vp, vp]
     P.pm_tune_set_small.argtypes = [ctypes.c_int, ctypes.c_uint, ctypes.c_uint, ctypes.c_uint]
     P.pm_tune_set_small_batch.argtypes = [sz]
+    P.pm_tune_set_pipeline.argtypes = [ctypes.c_int]
+    P.pm_tune_set_jobs_pipeline.argtypes = [ctypes.c_int]
     P.pm_polymul_jobs.argtypes = [ctypes.POINTER(lib.Job), sz, vp, sz, vp]
     P.pm_polymul_jobs_workspace_bytes.argtypes = [ctypes.POINTER(lib.Job), sz]
     P.pm_polymul_jobs_workspace_bytes.restype = sz
@@ -104,13 +108,46 @@ def test_poisoned_lds_parity(env, log2n, geo):
         P.pm_tune_set_small_batch(0)
 
 
-def test_poisoned_lds_jobs(env):
-    """Mixed sizes through the batched-jobs row kernels (rows of 2^12, and
-    whole small polynomials packed into one row task)."""
+@pytest.mark.parametrize("log2n", [15, 16, 17])
+def test_poisoned_lds_pipelined(env, log2n):
+    """The software-pipelined product (pm_tune_set_pipeline(2): rows of one
+    chunk beside the column passes of its neighbours in one launch) for
+    Eq. 2, the fused product and squaring, through the debug library."""
     import torch
     L, P = env
+    N, limbs, polys = 1 << log2n, 3, 2
+    qs = L.pm_ntt_primes(N, limbs)
+    prm = L.Params(N, limbs, primes=qs)
+    fw_o, iv_o = oracle_tables(qs, N)
+    a, b = operands(N, qs, polys, request=2700 + log2n)
+    want = oracle_polymul(a, b, qs, N, fw_o, iv_o)
+    want_sq = oracle_polymul(a, a, qs, N, fw_o, iv_o)
+    qarr = (ctypes.c_uint64 * limbs)(*qs)
+    ws = torch.empty(N * limbs * polys, dtype=torch.int64, device="cuda")
+    da, db = L.to_device(a), L.to_device(b)
+    P.pm_tune_set_pipeline(2)
+    try:
+        for fn, bp, w in (("pm_polymul", db, want), ("pm_polymul_fused", db, want), ("pm_polymul", da, want_sq)):
+            dc = torch.zeros_like(da)
+            _check(P, getattr(P, fn)(da.data_ptr(), bp.data_ptr(), dc.data_ptr(), N, limbs, polys, qarr,
+                                     prm.psi_br.data_ptr(), prm.psi_inv_br.data_ptr(), ws.data_ptr(), _stream()), fn)
+            torch.cuda.synchronize()
+            msg = first_mismatch(L.to_host(dc).reshape(a.shape), w)
+            assert msg is None, "%s%s N=%d: %s" % (fn, " (a = b)" if bp is da else "", N, msg)
+    finally:
+        P.pm_tune_set_pipeline(-1)
+
+
+@pytest.mark.parametrize("chunks", [0, 3], ids=["three-pass", "pipelined"])
+def test_poisoned_lds_jobs(env, chunks):
+    """Mixed sizes through the batched-jobs row kernels (rows of 2^12, and
+    whole small polynomials packed into one row task), as three launches and
+    as the software-pipelined launches."""
+    import torch
+    L, P = env
+    P.pm_tune_set_jobs_pipeline(chunks)
     jobs, keep, checks = [], [], []
-    for log2n in (5, 9, 12, 14, 16):
+    for log2n in (5, 9, 12, 14, 16, 17):
         N = 1 << log2n
         qs = L.pm_ntt_primes(N, 1)
         prm = L.Params(N, 1, primes=qs)
@@ -121,10 +158,13 @@ def test_poisoned_lds_jobs(env):
         keep += [prm, da, db, dc]
         checks.append((a, b, qs, N, dc))
     arr = (L.Job * len(jobs))(*jobs)
-    need = P.pm_polymul_jobs_workspace_bytes(arr, len(jobs))
-    ws = torch.empty(need // 8 + 64, dtype=torch.int64, device="cuda")
-    _check(P, P.pm_polymul_jobs(arr, len(jobs), ws.data_ptr(), ws.numel() * 8, _stream()), "jobs")
-    torch.cuda.synchronize()
+    try:
+        need = P.pm_polymul_jobs_workspace_bytes(arr, len(jobs))
+        ws = torch.empty(need // 8 + 64, dtype=torch.int64, device="cuda")
+        _check(P, P.pm_polymul_jobs(arr, len(jobs), ws.data_ptr(), ws.numel() * 8, _stream()), "jobs")
+        torch.cuda.synchronize()
+    finally:
+        P.pm_tune_set_jobs_pipeline(-1)
     for a, b, qs, N, dc in checks:
         fw, iv = oracle_tables(qs, N)
         msg = first_mismatch(L.to_host(dc).reshape(a.shape), oracle_polymul(a, b, qs, N, fw, iv))

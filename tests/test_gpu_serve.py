@@ -17,7 +17,7 @@ def ex():
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     from paper_2209_01290_amd import lib
     lib.load()
-    return serve.GpuExecutor(4 << 30, streams=3, pool=2, ws_bytes_per_stream=1 << 30)
+    return serve.GpuExecutor(4 << 30, streams=3, pool=2)
 
 
 def test_alone_equals_mix_and_oracle(ex):
@@ -53,7 +53,7 @@ def test_alone_equals_mix_and_oracle(ex):
 
 def test_small_budget_queues_and_completes(ex):
     trace = workloads.serving_requests(serve.SEED + 2, 120, 50000.0)
-    one = max(serve.footprint(n, L) for _, n, L in trace)
+    one = max(serve.request_bytes(n, L) for _, n, L in trace) + serve.BATCH_WS_SLACK
     eng = serve.Engine(ex, 2 * one, streams=3)
     st = eng.run(trace)
     assert st["completed"] == 120 and st["max_queue"] > 1
