@@ -115,6 +115,29 @@ int pm_polymul_fused(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t N
 size_t pm_polymul_workspace_bytes(size_t N, size_t limbs, size_t polys_per_limb);
 
 /*
+ * pm_polymul without a workspace argument and without any device allocation,
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments (minus workspace), result, aliasing rules and kernels as
+ * pm_polymul. The workspace lives in a fixed device array of this library,
+ * PM_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, created when the library is
+ * loaded on that GPU and held until the process ends; its address is looked
+ * up on the first call for each device (the stream's device).
+ * Limit: batches with pm_polymul_workspace_bytes(N, limbs, polys_per_limb)
+ * above PM_NOALLOC_SCRATCH_BYTES return PM_EINVAL before any work is queued
+ * (e.g. at most 128 products of N = 2^16, or 64 of N = 2^17, per call; batches
+ * needing no workspace have no limit).
+ * Every call on one GPU shares that GPU's array: calls that may overlap on one
+ * GPU (several streams or threads) race and must be serialised by the caller.
+ * The PM_VALIDATE scans (which allocate) and the event timer (pm_prof_*) do
+ * not apply to this entry point.
+ */
+#define PM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int pm_polymul_noalloc(const uint64_t *a, const uint64_t *b, uint64_t *c, size_t N, size_t limbs,
+                       size_t polys_per_limb, const uint64_t *q, const uint64_t *psi_br,
+                       const uint64_t *psi_inv_br, pm_stream_t stream);
+
+/*
  * The plain per-stage path (the paper's global-memory radix-2 baseline):
  * same result and arguments as pm_polymul, computed with one kernel launch per
  * NTT stage (each launch covers a and b of every limb), one pointwise launch

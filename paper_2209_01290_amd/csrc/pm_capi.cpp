@@ -364,7 +364,8 @@ uint32_t pipe_chunks(size_t np, uint32_t logr) {
 // Eq. 2 over a batch (fused: Alg. 8's rows instead of the pointwise rows).
 template <typename W>
 int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t polys, const W* q,
-                   const W* psi_br, const W* psi_inv_br, void* workspace, pm_stream_t stream, bool fused) {
+                   const W* psi_br, const W* psi_inv_br, void* workspace, pm_stream_t stream, bool fused,
+                   bool checks = true) {
   BatchT<W> b;
   int rc;
   if ((rc = check_batch(&b, N, limbs, polys, q))) return rc;
@@ -388,7 +389,7 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
   if (p.R > 1 && !same && (rc = check_ptr<W>(workspace, "workspace"))) return rc;
   W* ws = (W*)workspace;
   hipStream_t s = (hipStream_t)stream;
-  if (validate_enabled() &&
+  if (checks && validate_enabled() &&
       (rc = validate_batch<W>(b, {{a, "a"}, {b_, "b"}}, {{psi_br, "psi_br"}, {psi_inv_br, "psi_inv_br"}}, s)))
     return rc;
   rc = for_chunks(b, [&](size_t l0, size_t nl, const LimbSetT<W>& ls) -> hipError_t {
@@ -444,6 +445,25 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
 }
 
 }  // namespace
+
+namespace pm {
+
+// pm_polymul with the workspace supplied by the library itself (pm_noalloc.hip):
+// the PM_VALIDATE scans (which allocate) and the event timer are skipped.
+int polymul_fixed_workspace(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t N, size_t limbs,
+                            size_t polys, const uint64_t* q, const uint64_t* psi_br, const uint64_t* psi_inv_br,
+                            void* workspace, size_t workspace_cap, pm_stream_t stream) {
+  const size_t need = polymul_workspace<uint64_t>(N, limbs, polys);
+  if (need > workspace_cap)
+    return fail(PM_EINVAL, "pm_polymul_noalloc: this batch needs " + std::to_string(need) +
+                               " bytes of workspace, above the library's fixed " + std::to_string(workspace_cap) +
+                               "-byte scratch buffer");
+  ProfOff off;
+  return polymul_common(a, b, c, N, limbs, polys, q, psi_br, psi_inv_br, need ? workspace : nullptr, stream, false,
+                        false);
+}
+
+}  // namespace pm
 
 // ====================================================================== ABI ==
 

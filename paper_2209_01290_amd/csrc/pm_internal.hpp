@@ -112,4 +112,11 @@ hipError_t launch_reduce_apply(int variant, int word_bits, const uint64_t* a, co
 hipError_t launch_reduce_chain(int variant, int word_bits, uint64_t* out, size_t threads, uint64_t y, int iters,
                                const RedParams& P, hipStream_t s);
 
+// Eq. 2 over a batch with a caller-fixed workspace of workspace_cap bytes
+// (PM_EINVAL when the batch needs more); no device allocation, no PM_VALIDATE
+// scan, no event timer. stream is a hipStream_t (pm_capi.cpp).
+int polymul_fixed_workspace(const uint64_t* a, const uint64_t* b, uint64_t* c, size_t N, size_t limbs,
+                            size_t polys, const uint64_t* q, const uint64_t* psi_br, const uint64_t* psi_inv_br,
+                            void* workspace, size_t workspace_cap, void* stream);
+
 }  // namespace pm

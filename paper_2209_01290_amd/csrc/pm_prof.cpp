@@ -25,6 +25,7 @@ std::atomic<int> g_on{0};
 std::mutex g_mu;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_free;
+thread_local int g_off = 0;   // ProfOff nesting depth on this thread
 
 hipEvent_t take_event() {
   if (!g_free.empty()) {
@@ -39,8 +40,11 @@ hipEvent_t take_event() {
 
 }  // namespace
 
+ProfOff::ProfOff() { ++g_off; }
+ProfOff::~ProfOff() { --g_off; }
+
 ProfScope::ProfScope(hipStream_t s, const char* name) : s_(s), name_(name), slot_(-1) {
-  if (!g_on.load(std::memory_order_relaxed)) return;
+  if (g_off > 0 || !g_on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lk(g_mu);
   Rec r{name, take_event(), take_event(), false};
   if (!r.a || !r.b) return;

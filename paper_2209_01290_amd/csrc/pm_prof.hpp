@@ -18,4 +18,14 @@ class ProfScope {
   int slot_;
 };
 
+// While one is alive on a thread, ProfScope records nothing on that thread
+// (entry points that must not create events or touch host-side pools).
+class ProfOff {
+ public:
+  ProfOff();
+  ~ProfOff();
+  ProfOff(const ProfOff&) = delete;
+  ProfOff& operator=(const ProfOff&) = delete;
+};
+
 }  // namespace pm

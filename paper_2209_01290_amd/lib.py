@@ -68,6 +68,7 @@ def load():
             "pm_ntt_inv": (i32, [vp, sz, sz, sz, u64p, vp, vp]),
             "pm_polymul": (i32, [vp, vp, vp, sz, sz, sz, u64p, vp, vp, vp, vp]),
             "pm_polymul_workspace_bytes": (sz, [sz, sz, sz]),
+            "pm_polymul_noalloc": (i32, [vp, vp, vp, sz, sz, sz, u64p, vp, vp, vp]),
             "pm_polymul_fused": (i32, [vp, vp, vp, sz, sz, sz, u64p, vp, vp, vp, vp]),
             "pm_polymul_stagewise": (i32, [vp, vp, vp, sz, sz, sz, u64p, vp, vp, vp, vp]),
             "pm_polymul_stagewise_workspace_bytes": (sz, [sz, sz, sz]),
@@ -121,7 +122,7 @@ def load():
 def exported_symbols():
     """Names of the C entry points this binding declares."""
     return ["pm_last_error", "pm_barrett_mulmod", "pm_ntt_fwd", "pm_ntt_inv", "pm_polymul", "pm_polymul_fused",
-            "pm_polymul_workspace_bytes", "pm_polymul_stagewise",
+            "pm_polymul_workspace_bytes", "pm_polymul_noalloc", "pm_polymul_stagewise",
             "pm_polymul_stagewise_workspace_bytes", "pm_tune_set", "pm_tune_get",
             "pm_ntt_primes", "pm_find_psi", "pm_make_tables", "pm_prof_enable", "pm_prof_read", "pm_probe_valu",
             "pm_polymul_jobs_workspace_bytes", "pm_polymul_jobs", "pm_plan_create", "pm_plan_launch",
@@ -239,6 +240,16 @@ def pm_polymul(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspa
     _check(load().pm_polymul(_dptr(a, "a"), _dptr(b, "b"), _dptr(c, "c"), N, limbs, polys_per_limb,
                              _qarr(q, limbs), _dptr(psi_br, "psi_br"), _dptr(psi_inv_br, "psi_inv_br"),
                              _dptr(workspace, "workspace"), _stream(stream, a)), "pm_polymul")
+
+
+def pm_polymul_noalloc(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, stream=None):
+    """pm_polymul with its workspace in the library's fixed per-GPU scratch array (no allocation)."""
+    _check(load().pm_polymul_noalloc(_dptr(a, "a"), _dptr(b, "b"), _dptr(c, "c"), N, limbs, polys_per_limb,
+                                     _qarr(q, limbs), _dptr(psi_br, "psi_br"), _dptr(psi_inv_br, "psi_inv_br"),
+                                     _stream(stream, a)), "pm_polymul_noalloc")
+
+
+PM_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def pm_polymul_fused(a, b, c, N, limbs, polys_per_limb, q, psi_br, psi_inv_br, workspace=None, stream=None):
