@@ -24,6 +24,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/pm.h"
@@ -118,6 +119,33 @@ bool plan_pipeline(Layout* L, const std::vector<uint32_t>& pjobs, uint32_t G) {
   return true;
 }
 
+// The order in which jobs enter the work-item maps. Every transform of a row
+// reads about as many twiddle words as it has coefficients, so jobs that
+// share a table (same N and modulus: e.g. limb l of every request of size N)
+// are placed next to each other, where the tables of neighbouring work items
+// are still in cache. The groups of each size are interleaved (group k of
+// every size before group k + 1 of any), so that every chunk of the
+// pipelined form still mixes sizes. Ties keep the caller's order.
+std::vector<uint32_t> table_order(const std::vector<JobDev>& jobs) {
+  const size_t n = jobs.size();
+  std::vector<uint32_t> rank(n, 0);
+  std::vector<uint32_t> per_size(PM_MAX_LOG2N + 1, 0);   // tables seen so far, per size
+  std::vector<std::unordered_map<const uint64_t*, uint32_t>> table_rank(PM_MAX_LOG2N + 1);
+  for (size_t j = 0; j < n; ++j) {
+    const uint32_t ln = jobs[j].log2n;
+    auto it = table_rank[ln].find(jobs[j].tf);
+    if (it == table_rank[ln].end()) it = table_rank[ln].emplace(jobs[j].tf, per_size[ln]++).first;
+    rank[j] = it->second;
+  }
+  std::vector<uint32_t> order(n);
+  for (size_t j = 0; j < n; ++j) order[j] = (uint32_t)j;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    if (rank[x] != rank[y]) return rank[x] < rank[y];
+    return jobs[x].log2n < jobs[y].log2n;
+  });
+  return order;
+}
+
 int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
   if (!jobs || njobs == 0) return set_error(PM_EINVAL, "empty job list");
   if (njobs > (1u << 24)) return set_error(PM_EINVAL, "too many jobs");
@@ -154,10 +182,11 @@ int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
   }
   const int set = g_jobs_pipe.load();
   const bool pipelined = set != 0 && set != 1 && pipe_rows >= (set > 1 ? 1 : JOBS_PIPE_MIN_ROWS);
+  const std::vector<uint32_t> order = table_order(L->jobs);
   size_t ws = 0;
   std::vector<size_t> ws_job(njobs, 0);
   std::vector<uint32_t> pjobs;
-  for (size_t j = 0; j < njobs; ++j) {
+  for (const uint32_t j : order) {
     JobDev& J = L->jobs[j];
     const bool pj = pipelined && J.log2n >= 12;
     if (pj) {
@@ -174,9 +203,9 @@ int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
       ws += ((size_t)J.count << J.log2n) * sizeof(uint64_t);
     }
   }
-  // work items, in job order within each map; every phase's first item is
-  // recorded (also when the job has none in that phase)
-  for (size_t j = 0; j < njobs; ++j) {
+  // work items, in the table order within each map; every phase's first
+  // item is recorded (also when the job has none in that phase)
+  for (const uint32_t j : order) {
     JobDev& J = L->jobs[j];
     const uint32_t R = 1u << J.logr;
     const bool pj = pipelined && J.log2n >= 12;
