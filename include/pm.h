@@ -324,7 +324,7 @@ int pm_tune_get_pipeline(void);
  * chunk j-1, the forward column pass of chunk j and the inverse column pass
  * of chunk j-2, with any mix of sizes and moduli in one launch. Jobs of
  * N < 2^12 run their single row pass in a launch before the pipeline.
- * chunks = -1 (the default): G = rows / 8192 within [2, 16]; 0 or 1: never
+ * chunks = -1 (the default): G = rows / 24576 within [2, 16]; 0 or 1: never
  * pipelined (three launches, one per pass of Eq. 2, with the tuned splits);
  * G >= 2: G chunks (at most 256; more where a launch would exceed the grid
  * limit), pipelined whenever the batch has such a job. Results are

@@ -57,7 +57,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Pipelined form: used from this many rows of 2^12 words (jobs of N >= 2^12);
 // chunks chosen by default as rows / JOBS_PIPE_ROWS_PER_CHUNK, within
 // [2, JOBS_PIPE_MAX_AUTO]; at most JOBS_PIPE_MAX_CHUNKS when set.
-constexpr uint64_t JOBS_PIPE_MIN_ROWS = 2048, JOBS_PIPE_ROWS_PER_CHUNK = 8192;
+constexpr uint64_t JOBS_PIPE_MIN_ROWS = 2048, JOBS_PIPE_ROWS_PER_CHUNK = 24576;
 constexpr uint32_t JOBS_PIPE_MAX_AUTO = 16, JOBS_PIPE_MAX_CHUNKS = 256;
 std::atomic<int> g_jobs_pipe{-1};
 
