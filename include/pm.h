@@ -316,6 +316,20 @@ int pm_tune_set_pipeline(int chunks);
 int pm_tune_get_pipeline(void);
 
 /*
+ * The threshold of the default (chunks = -1) pipelining above, per column
+ * radix 2^logr (logr = 3, 4, 5: N = 2^15, 2^16, 2^17 with rows of 2^12
+ * words): a launch group is pipelined over 2 chunks when its row pass has
+ * at least min_rows rows. min_rows = 0 restores the built-in value (2048;
+ * 8192 for logr = 5); SIZE_MAX never pipelines that radix. The autotuner
+ * measures it (tune.py --pipeline) and lib.apply_tune_db installs it.
+ * Process-wide, read when a call is made. PM_EINVAL for logr outside 3..5;
+ * pm_tune_get_pipeline_rows returns the threshold in effect (0 for an
+ * invalid logr).
+ */
+int pm_tune_set_pipeline_rows(unsigned logr, size_t min_rows);
+size_t pm_tune_get_pipeline_rows(unsigned logr);
+
+/*
  * Software pipelining of job tables (pm_polymul_jobs, pm_plan_create): a
  * batch whose jobs of N >= 2^12 hold at least 2048 rows of 2^12 words runs
  * those jobs with rows of 2^12 words, their products split into G chunks of

@@ -346,16 +346,16 @@ size_t polymul_workspace(size_t N, size_t limbs, size_t polys) {
 
 // Chunks of the software-pipelined product for a launch group of np
 // products with a column radix of 2^logr, unless pm_tune_set_pipeline chose:
-// 2 when the row pass has at least PIPE_MIN_ROWS rows (PIPE_MIN_ROWS_R32 for
-// radix 32), else 0 (the three-pass form). Each chunk's rows are one more
-// phase on the critical path, and a row workgroup alone on its CU is bound by
-// latency, so the overlap pays only once the rows fill the CUs several times
-// over. At most PIPE_MAX_CHUNKS chunks and at most np.
-constexpr size_t PIPE_MIN_ROWS = 2048, PIPE_MIN_ROWS_R32 = 8192, PIPE_MAX_CHUNKS = 64;
+// 2 when the row pass has at least plan_pipe_rows(logr) rows (2048, 8192 for
+// radix 32, unless tuned), else 0 (the three-pass form). Each chunk's rows
+// are one more phase on the critical path, and a row workgroup alone on its
+// CU is bound by latency, so the overlap pays only once the rows fill the CUs
+// several times over. At most PIPE_MAX_CHUNKS chunks and at most np.
+constexpr size_t PIPE_MAX_CHUNKS = 64;
 uint32_t pipe_chunks(size_t np, uint32_t logr) {
   const int set = plan_pipe();
   const size_t rows = np << logr;
-  size_t g = set >= 0 ? (size_t)set : (rows >= (logr >= 5 ? PIPE_MIN_ROWS_R32 : PIPE_MIN_ROWS) ? 2 : 0);
+  size_t g = set >= 0 ? (size_t)set : (rows >= plan_pipe_rows(logr) ? 2 : 0);
   if (g > PIPE_MAX_CHUNKS) g = PIPE_MAX_CHUNKS;
   if (g > np) g = np;
   return g > 1 ? (uint32_t)g : 0u;

@@ -83,6 +83,24 @@ bool plan_small_limit_set(int op, unsigned log2n, size_t words) {
 void plan_pipe_set(int chunks) { g_pipe.store(chunks < 0 ? -1 : chunks); }
 int plan_pipe() { return g_pipe.load(); }
 
+namespace {
+// built-in thresholds, from a sweep of batch sizes on MI355X (2^15..2^17)
+constexpr size_t PIPE_MIN_ROWS_DEFAULT[3] = {2048, 2048, 8192};
+std::atomic<size_t> g_pipe_rows[3] = {{0}, {0}, {0}};
+}  // namespace
+
+bool plan_pipe_rows_set(unsigned logr, size_t min_rows) {
+  if (logr < 3 || logr > 5) return false;
+  g_pipe_rows[logr - 3].store(min_rows);
+  return true;
+}
+
+size_t plan_pipe_rows(unsigned logr) {
+  if (logr < 3 || logr > 5) return 0;
+  const size_t v = g_pipe_rows[logr - 3].load();
+  return v ? v : PIPE_MIN_ROWS_DEFAULT[logr - 3];
+}
+
 size_t plan_small_limit(int op, unsigned log2n) {
   if (op < 0 || op >= OP_COUNT || log2n < 1 || log2n > PM_MAX_LOG2N) return 0;
   return g_small_limit[op][log2n].load();
@@ -159,3 +177,9 @@ extern "C" int pm_tune_set_pipeline(int chunks) {
 }
 
 extern "C" int pm_tune_get_pipeline(void) { return pm::plan_pipe(); }
+
+extern "C" int pm_tune_set_pipeline_rows(unsigned logr, size_t min_rows) {
+  return pm::plan_pipe_rows_set(logr, min_rows) ? PM_OK : PM_EINVAL;
+}
+
+extern "C" size_t pm_tune_get_pipeline_rows(unsigned logr) { return pm::plan_pipe_rows(logr); }

@@ -47,5 +47,9 @@ size_t plan_small_limit(int op, unsigned log2n);
 // 0 or 1 = never pipelined, G >= 2 = G chunks (at most the launch group's limbs).
 void plan_pipe_set(int chunks);
 int plan_pipe();
+// Rows of 2^12 words from which the default pipelines a launch group, per
+// column radix 2^logr (3..5); 0 = the built-in value. False for other logr.
+bool plan_pipe_rows_set(unsigned logr, size_t min_rows);
+size_t plan_pipe_rows(unsigned logr);     // the threshold in effect
 
 }  // namespace pm

@@ -83,6 +83,8 @@ def load():
             "pm_tune_get_small_limit": (sz, [i32, ctypes.c_uint]),
             "pm_tune_set_pipeline": (i32, [i32]),
             "pm_tune_get_pipeline": (i32, []),
+            "pm_tune_set_pipeline_rows": (i32, [ctypes.c_uint, sz]),
+            "pm_tune_get_pipeline_rows": (sz, [ctypes.c_uint]),
             "pm_tune_set_jobs_pipeline": (i32, [i32]),
             "pm_tune_get_jobs_pipeline": (i32, []),
             "pm_ntt_primes": (sz, [u64, ctypes.c_uint, sz, u64p]),
@@ -133,7 +135,7 @@ def exported_symbols():
             "pm_polymul_il_workspace_bytes", "pm_tune_set_small", "pm_tune_get_small",
             "pm_tune_set_small_batch", "pm_tune_get_small_batch", "pm_tune_set_small_limit",
             "pm_tune_get_small_limit", "pm_tune_set_pipeline", "pm_tune_get_pipeline",
-            "pm_tune_set_jobs_pipeline",
+            "pm_tune_set_pipeline_rows", "pm_tune_get_pipeline_rows", "pm_tune_set_jobs_pipeline",
             "pm_tune_get_jobs_pipeline"]
 
 
@@ -433,6 +435,16 @@ def pm_tune_set_pipeline(chunks):
     _check(load().pm_tune_set_pipeline(int(chunks)), "pm_tune_set_pipeline")
 
 
+def pm_tune_set_pipeline_rows(logr, min_rows):
+    """Rows of 2^12 words from which the default pipelines a product with column
+    radix 2^logr (3..5); 0 = built-in value."""
+    _check(load().pm_tune_set_pipeline_rows(int(logr), int(min_rows)), "pm_tune_set_pipeline_rows")
+
+
+def pm_tune_get_pipeline_rows(logr):
+    return int(load().pm_tune_get_pipeline_rows(int(logr)))
+
+
 def pm_tune_set_jobs_pipeline(chunks):
     """Chunks of the software-pipelined job tables: -1 automatic, 0 off, G >= 2 forced."""
     _check(load().pm_tune_set_jobs_pipeline(int(chunks)), "pm_tune_set_jobs_pipeline")
@@ -451,7 +463,8 @@ def apply_tune_db(path=None):
     $PM_TUNE_DB, else the packaged MI355X database): the
     throughput plans ("choices") and, if present, the small-batch plans
     ("small": {"max_words": W, "choices": {op: {log2n: [logc, words_per_thread]}},
-    "limits": {op: {log2n: words}}}, the limits replacing W for their (op, N));
+    "limits": {op: {log2n: words}}}, the limits replacing W for their (op, N))
+    and the pipelining thresholds ("pipeline": {"min_rows": {logr: rows}});
     returns the number of entries applied, 0 if the file does not exist."""
     import json
     if path is None:
@@ -477,6 +490,11 @@ def apply_tune_db(path=None):
                 pm_tune_set_small_limit(ops[name], int(log2n), int(words))
                 n += 1
         pm_tune_set_small_batch(int(small["max_words"]))
+    pipe = db.get("pipeline")
+    if pipe:
+        for logr, rows in pipe.get("min_rows", {}).items():
+            pm_tune_set_pipeline_rows(int(logr), int(rows))
+            n += 1
     return n
 
 

@@ -22,7 +22,15 @@ other sizes:
               "limits": {"polymul": {"16": words, ...}, ...},
               "latency_us": {...}, "crossover_us": {...}}
 
-Usage on a GPU:  python -m paper_2209_01290_amd.tune [--out FILE] [--log2n 12-17] [--small]
+Pipelining thresholds (--pipeline): for N = 2^15..2^17 (rows of 2^12 words
+after a column pass of radix 2^3..2^5) the product over 16..480 products is
+timed with the software pipeline (two chunks) and with three passes in
+alternating blocks; per radix, the row count from which pipelining every
+larger batch minimises the summed relative time over the measured batches:
+
+    "pipeline": {"min_rows": {"3": rows, "4": rows, "5": rows}, "timings_ms": {...}}
+
+Usage on a GPU:  python -m paper_2209_01290_amd.tune [--out FILE] [--log2n 12-17] [--small | --pipeline]
 Applying a database: lib.apply_tune_db(FILE) (bench.py and serve.py do).
 """
 from __future__ import annotations
@@ -244,14 +252,105 @@ def tune_small(log2ns, device="cuda", verbose=True):
             "crossover_us": cross}
 
 
+# batch shapes (limbs, pairs per limb): 16..480 products
+PIPE_SHAPES = ((16, 1), (32, 1), (48, 1), (48, 2), (48, 3), (48, 4), (48, 5), (48, 6), (48, 8), (48, 10))
+NEVER = (1 << 64) - 1
+
+
+def tune_pipeline(log2ns=(15, 16, 17), shapes=PIPE_SHAPES, device="cuda", verbose=True, reps=4, calls=10):
+    """The threshold of the default software pipelining, per column radix
+    2^logr (N = 2^(12 + logr), rows of 2^12 words): for each batch shape the
+    product is timed with two chunks and with three passes in alternating
+    blocks, after the tuned plans are installed; the threshold is the row
+    count (products x 2^logr) from which pipelining every larger measured
+    batch gives the least summed time over all measured batches, each
+    relative to its three-pass time (never, if no threshold beats three
+    passes everywhere). Installs the thresholds with
+    pm_tune_set_pipeline_rows."""
+    import time
+    import torch
+    from . import lib, synth
+    lib.load()
+    lib.apply_tune_db()
+    dev = torch.device(device)
+    stream = torch.cuda.current_stream(dev)
+    min_rows, timings = {}, {}
+    for log2n in log2ns:
+        N, logr = 1 << log2n, log2n - 12
+        res = {}
+        for limbs, polys in shapes:
+            P = limbs * polys
+            prm = lib.Params(N, limbs, device=dev)
+            a, b = synth.operands(synth.SEED_BASE + 19, prm.q, 1, N)
+            da = lib.to_device(a, dev).repeat(1, polys, 1).contiguous()
+            db = lib.to_device(b, dev).repeat(1, polys, 1).contiguous()
+            dc = torch.empty_like(da)
+            ws = torch.empty(max(lib.pm_polymul_workspace_bytes(N, limbs, polys) // 8, 1), dtype=torch.int64,
+                             device=dev)
+
+            def step():
+                lib.pm_polymul(da, db, dc, N, limbs, polys, prm.q, prm.psi_br, prm.psi_inv_br, ws)
+
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < 0.3:       # settle the clock
+                for _ in range(calls):
+                    step()
+                torch.cuda.synchronize()
+            per = {0: [], 2: []}
+            for _ in range(reps):
+                for g in (0, 2):
+                    lib.pm_tune_set_pipeline(g)
+                    step()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(calls):
+                        step()
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    per[g].append(e0.elapsed_time(e1) / calls)
+            lib.pm_tune_set_pipeline(-1)
+            three, pipe = sorted(per[0])[reps // 2], sorted(per[2])[reps // 2]
+            res[P] = (three, pipe)
+            if verbose:
+                print("[tune-pipe] N=2^%d %4d products (%6d rows): three-pass %.4f ms, two chunks %.4f ms (%.3fx)"
+                      % (log2n, P, P << logr, three, pipe, three / pipe), flush=True)
+            del da, db, dc, ws
+        # the threshold that minimises the summed time of the measured batch
+        # sizes, each relative to its three-pass time (so that every size
+        # counts alike): batches from the threshold up run pipelined
+        rows, best = NEVER, float(len(res))
+        for cut in sorted(res):
+            cost = sum(1.0 if P < cut else pipe / three for P, (three, pipe) in res.items())
+            if cost < best - 1e-9:
+                rows, best = cut << logr, cost
+        lib.pm_tune_set_pipeline_rows(logr, rows)
+        min_rows[str(logr)] = rows
+        timings[str(log2n)] = {str(P): [round(t, 4), round(p, 4)] for P, (t, p) in res.items()}
+        if verbose:
+            print("[tune-pipe] N=2^%d: pipelined from %s rows" % (log2n, "never" if rows == NEVER else rows),
+                  flush=True)
+    return {"min_rows": min_rows, "timings_ms": timings,
+            "what": "per column radix 2^logr: rows of 2^12 words from which two chunks beat three passes; "
+                    "timings [three-pass, two chunks] ms per call by products"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_DB)
     ap.add_argument("--log2n", default="1-17", help="range lo-hi of log2 N")
     ap.add_argument("--small", action="store_true",
                     help="tune only the small-batch plans and merge them into --out")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="tune only the thresholds of the software-pipelined product and merge them into --out")
     a = ap.parse_args()
     lo, hi = (int(v) for v in a.log2n.split("-"))
+    if a.pipeline:
+        db = json.load(open(a.out)) if os.path.exists(a.out) else {}
+        db["pipeline"] = tune_pipeline()
+        with open(a.out, "w") as f:
+            json.dump(db, f, indent=1)
+        print("[tune] wrote " + a.out, flush=True)
+        return
     if a.small:
         db = json.load(open(a.out)) if os.path.exists(a.out) else {}
         db["small"] = tune_small(range(lo, hi + 1))
@@ -262,8 +361,9 @@ def main():
     db = tune(range(lo, hi + 1))
     if os.path.exists(a.out):
         old = json.load(open(a.out))
-        if "small" in old:
-            db["small"] = old["small"]          # the small-batch plans are tuned separately
+        for part in ("small", "pipeline"):      # tuned separately
+            if part in old:
+                db[part] = old[part]
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(db, f, indent=1)

@@ -89,6 +89,8 @@ class tuned:
                 L.pm_tune_set_small_limit(op, n, 0)
         L.pm_tune_set_small_batch(0)
         L.pm_tune_set_pipeline(-1)
+        for logr in (3, 4, 5):
+            L.pm_tune_set_pipeline_rows(logr, 0)
         L.pm_tune_set_jobs_pipeline(-1)
         return False
 

@@ -125,7 +125,10 @@ def test_tune_db_applies(L, tmp_path):
         n = L.apply_tune_db()
         assert n == sum(len(t) for t in shipped["choices"].values()) + \
             sum(len(t) for t in shipped["small"]["choices"].values()) + \
-            sum(len(t) for t in shipped["small"].get("limits", {}).values())
+            sum(len(t) for t in shipped["small"].get("limits", {}).values()) + \
+            len(shipped.get("pipeline", {}).get("min_rows", {}))
+        for logr, rows in shipped.get("pipeline", {}).get("min_rows", {}).items():
+            assert L.pm_tune_get_pipeline_rows(int(logr)) == rows
         assert L.pm_tune_get_small_batch() == shipped["small"]["max_words"] > 0
         assert L.pm_tune_get_small(L.OP_POLYMUL, 16) == tuple(shipped["small"]["choices"]["polymul"]["16"])
         ops = {"polymul": L.OP_POLYMUL, "ntt_fwd": L.OP_NTT_FWD, "ntt_inv": L.OP_NTT_INV}
@@ -139,6 +142,8 @@ def test_tune_db_applies(L, tmp_path):
                 L.pm_tune_set_small(op, n, 0, 0)
                 L.pm_tune_set_small_limit(op, n, 0)
         L.pm_tune_set_small_batch(0)
+        for logr in (3, 4, 5):
+            L.pm_tune_set_pipeline_rows(logr, 0)
 
 
 def test_u32_invalid_arguments_rejected_on_host(L):
@@ -254,3 +259,33 @@ def test_pipeline_setting():
             assert L.pm_polymul_workspace_bytes(N, 48, 8) == ws
     finally:
         L.pm_tune_set_pipeline(-1)
+
+
+def test_pipeline_rows_setting():
+    """pm_tune_set_pipeline_rows: per column radix 2^3..2^5, 0 restores the
+    built-in threshold (2048; 8192 for radix 32), other radices are rejected;
+    the packaged database installs its tuned thresholds."""
+    from paper_2209_01290_amd import lib as L
+    L.load()
+    before = {r: L.pm_tune_get_pipeline_rows(r) for r in (3, 4, 5)}
+    try:
+        for r in (3, 4, 5):
+            L.pm_tune_set_pipeline_rows(r, 0)
+        assert [L.pm_tune_get_pipeline_rows(r) for r in (3, 4, 5)] == [2048, 2048, 8192]
+        L.pm_tune_set_pipeline_rows(4, 12345)
+        assert L.pm_tune_get_pipeline_rows(4) == 12345
+        L.pm_tune_set_pipeline_rows(5, (1 << 64) - 1)
+        assert L.pm_tune_get_pipeline_rows(5) == (1 << 64) - 1
+        for bad in (0, 2, 6, 17):
+            with pytest.raises(L.PMError) as ei:
+                L.pm_tune_set_pipeline_rows(bad, 100)
+            assert ei.value.code == L.PM_EINVAL
+            assert L.pm_tune_get_pipeline_rows(bad) == 0
+        import json, os
+        db = json.load(open(os.path.join(os.path.dirname(L.__file__), "tune_db", "gfx950.json")))
+        L.apply_tune_db()
+        for logr, rows in db.get("pipeline", {}).get("min_rows", {}).items():
+            assert L.pm_tune_get_pipeline_rows(int(logr)) == int(rows)
+    finally:
+        for r, v in before.items():
+            L.pm_tune_set_pipeline_rows(r, v)

@@ -245,3 +245,56 @@ def test_jobs_pipelined_automatic_at_threshold(L):
             want = o.polymul_ntt(a[0, p], b[0, p], q, fw[0], iv[0])
             msg = first_mismatch(piped[i].reshape(count, -1)[p], want)
             assert msg is None, "job %d product %d: %s" % (i, p, msg)
+
+
+@pytest.mark.parametrize("chunks", [0, 3])
+def test_jobs_order_independent(L, chunks):
+    """The work-item maps list jobs grouped by twiddle table, not in the
+    caller's order: the same jobs given in another order (tables shared by
+    several jobs of one size, sizes interleaved differently) produce the same
+    words, in the three-pass and the pipelined form, and match the oracle."""
+    import torch
+    spec = []   # (log2n, count, prime index): three tables per size, each used by several jobs
+    for r in range(3):
+        for log2n in (12, 13, 15, 16, 17):
+            for qi in (0, 1, 2):
+                spec.append((log2n, 1 + (r + qi) % 2, qi))
+    rng = np.random.default_rng(20901290)
+    tables, jobs, keep = {}, [], []
+    for i, (log2n, count, qi) in enumerate(spec):
+        N = 1 << log2n
+        if (log2n, qi) not in tables:
+            q = L.pm_ntt_primes(N, qi + 1)[qi]
+            fw, iv = L.pm_make_tables(q, N)
+            tables[(log2n, qi)] = (q, L.to_device(fw), L.to_device(iv))
+        q, dfw, div = tables[(log2n, qi)]
+        a, b = synth.operands(synth.SEED_BASE + 8, [q], count, N, request=i)
+        da, db = L.to_device(a[0]), L.to_device(b[0])
+        keep.append([da, db, torch.empty_like(da), a, b, q, log2n, count])
+        jobs.append((log2n, count, q, dfw, div))
+    outs = []
+    L.pm_tune_set_jobs_pipeline(chunks)
+    try:
+        for perm in (np.arange(len(spec)), rng.permutation(len(spec)), np.arange(len(spec))[::-1]):
+            for k in keep:
+                k[2].fill_(-1)
+            job_list = [L.make_job(jobs[i][0], jobs[i][1], jobs[i][2], jobs[i][3], jobs[i][4],
+                                   keep[i][0], keep[i][1], keep[i][2]) for i in perm]
+            nbytes = max(L.pm_polymul_jobs_workspace_bytes(job_list), 8)
+            ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device="cuda")
+            L.pm_polymul_jobs(job_list, ws)
+            torch.cuda.synchronize()
+            outs.append([L.to_host(k[2]).copy() for k in keep])
+    finally:
+        L.pm_tune_set_jobs_pipeline(-1)
+    for j in (1, 2):
+        for i in range(len(spec)):
+            assert np.array_equal(outs[0][i], outs[j][i]), "job %d differs between orders 0 and %d" % (i, j)
+    import oracle
+    o = oracle.default()
+    for i in range(0, len(spec), 7):
+        da, db, dc, a, b, q, log2n, count = keep[i]
+        fw, iv = oracle_tables([q], 1 << log2n)
+        want = o.polymul_ntt(a[0, count - 1], b[0, count - 1], q, fw[0], iv[0])
+        msg = first_mismatch(outs[0][i].reshape(count, -1)[count - 1], want)
+        assert msg is None, "job %d (N=2^%d): %s" % (i, log2n, msg)

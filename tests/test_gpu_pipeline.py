@@ -173,15 +173,20 @@ def test_pipelined_launch_groups(L):
 
 def test_pipelined_benchmark_plan(L):
     """The tuned plans pipeline the benchmark's 2^16 product by default (here
-    2 limbs x 64 pairs: 2048 rows)."""
-    N, limbs, polys = 1 << 16, 2, 64
+    2 limbs x 96 pairs: 3072 rows, at the tuned threshold) and keep the
+    three passes just below it (2 x 95 pairs)."""
+    N, limbs, polys = 1 << 16, 2, 96
     qs = L.pm_ntt_primes(N, limbs)
     _, _, dfw, div = device_tables(qs, N)
     a, b = operands(N, qs, polys, request=795)
     with tuned(L):
         assert L.pm_tune_get(L.OP_POLYMUL, 16) == 12
+        assert L.pm_tune_get_pipeline_rows(4) == limbs * polys * 16
         got, prof = _run(L, L.pm_polymul, a, b, N, qs, dfw, div, -1)
+        below, prof_b = _run(L, L.pm_polymul, a[:, :95].copy(), b[:, :95].copy(), N, qs, dfw, div, -1)
     assert prof.get("pipe_mul_c12") == 4, prof
+    assert "pipe_mul_c12" not in prof_b, prof_b
+    _assert_equal(below, got[:, :95], "three passes below the threshold vs pipelined")
     fw_o, iv_o = oracle_tables(qs, N)
     want = oracle_polymul(a[:, :3], b[:, :3], qs, N, fw_o, iv_o)
     _assert_equal(got[:, :3], want, "tuned plan, first three pairs per limb")
