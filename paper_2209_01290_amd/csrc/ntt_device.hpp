@@ -26,6 +26,9 @@
 //
 // Column pass. One thread per column holds the R = 2^s words of that column
 // in registers and runs the s column stages; twiddles are uniform per launch.
+// In the software-pipelined kernels a 32-word column (s = 5) is held by two
+// lanes of one wave instead, 16 words each (col32_fwd_pair below), so that the
+// column code needs no more registers than the row code beside it.
 #pragma once
 #include "modarith.hpp"
 #include "modarith32.hpp"
@@ -345,6 +348,56 @@ __device__ __forceinline__ void blk_inv(W (&x)[1 << LOGR], const W* __restrict__
       for (int s = 0; s < k; ++s) gs_bfly_htw<KIND>(x[2 * g * k + s], x[2 * g * k + s + k], xh, M);
     }
   }
+}
+
+// Exchange between the two halves of a wave (v_permlane32_swap, gfx950).
+// Afterwards lanes 32..63 hold in p what lanes 0..31 held in q, and lanes
+// 0..31 hold in q what lanes 32..63 held in p; lanes 0..31 keep p and lanes
+// 32..63 keep q. Every lane of the wave must be active.
+__device__ __forceinline__ void half_swap(uint32_t& p, uint32_t& q) {
+  const auto r = __builtin_amdgcn_permlane32_swap(p, q, false, false);
+  p = r[0];
+  q = r[1];
+}
+
+__device__ __forceinline__ void half_swap(uint64_t& p, uint64_t& q) {
+  uint32_t p0 = lo32(p), p1 = hi32(p), q0 = lo32(q), q1 = hi32(q);
+  half_swap(p0, q0);
+  half_swap(p1, q1);
+  p = pack64(p0, p1);
+  q = pack64(q0, q1);
+}
+
+// Column pass of R = 32 words held by the lanes l and l + 32 of one wave
+// (h = 0 and 1), 16 words each. The first stage of Alg. 5 (stride 16 rows)
+// pairs row i with row i + 16, so half h starts with rows
+// col32_split_row(j, h) = (j & 7) + 8h + 16 (j >> 3) in y[j]: y[k] and y[8+k]
+// are the pairs of that stage. One exchange of eight words (y[8+k] of h = 0
+// with y[k] of h = 1) then leaves half h with rows 16h + j in y[j], the block
+// of rows whose last four column stages use the twiddles of blk_fwd with
+// rb = 2 + h. The inverse (Alg. 6, halved) runs the same steps in reverse
+// order: the block's four stages, the same exchange, then the stride-16 stage.
+__device__ __forceinline__ uint32_t col32_split_row(int j, uint32_t h) { return (j & 7) + 8 * h + 16 * (j >> 3); }
+__device__ __forceinline__ uint32_t col32_block_row(int j, uint32_t h) { return 16 * h + j; }
+
+template <int KIND, typename W, typename MT>
+__device__ __forceinline__ void col32_fwd_pair(W (&y)[16], const W* __restrict__ tw, uint32_t h, const MT& M) {
+  const W xi = tw[1];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ct_bfly<KIND>(y[k], y[8 + k], xi, M);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) half_swap(y[k], y[8 + k]);
+  blk_fwd<4, KIND>(y, tw, 2 + h, M);
+}
+
+template <int KIND, typename W, typename MT>
+__device__ __forceinline__ void col32_inv_pair(W (&y)[16], const W* __restrict__ tw, uint32_t h, const MT& M) {
+  blk_inv<4, KIND>(y, tw, 2 + h, M);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) half_swap(y[k], y[8 + k]);
+  const W xh = half_tw(tw[1], M);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) gs_bfly_htw<KIND>(y[k], y[8 + k], xh, M);
 }
 
 }  // namespace pm

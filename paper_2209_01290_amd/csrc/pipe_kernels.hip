@@ -26,26 +26,20 @@ namespace {
 constexpr int PIPE_LC = 12;                        // row length 2^12 (16 words per thread)
 using PG = RowGeom<PIPE_LC>;
 static_assert(PG::WG == 256 && PG::ROWS == 1, "one 2^12-word row per workgroup of 256 threads");
-// column blocks of 256 per polynomial: the host sizes a chunk's forward-column
-// grid as nops * PIPE_CB and its inverse-column grid as PIPE_CB per product
-constexpr uint32_t PIPE_CB = (1u << PIPE_LC) / 256;
-static_assert(PIPE_CB == 16, "pm_capi.cpp launches 16 column workgroups per product and operand");
+static_assert(pipe_col_blocks(3) == (1u << PIPE_LC) / 256 && pipe_col_blocks(5) == (1u << PIPE_LC) / 128,
+              "column blocks of 256 columns, of 128 columns for a 32-word column on two lanes");
 
 // grid: nr row workgroups, then nf forward-column and ni inverse-column ones.
 // A chunk is a range of products (limb-major: product p = limb * polys + poly,
-// stored at p * N), so a chunk may end inside a limb.
-// Waves per SIMD the register budget is set for: the row modes' own budget,
-// and 3 with a 32-word column in registers (4 would spill it).
-template <int LOGR, int MODE>
-struct PipeWaves {
-  static constexpr int value = LOGR >= 5 ? 3 : RowWaves<MODE>::value;
-};
-
+// stored at p * N), so a chunk may end inside a limb. Every kind of work
+// item fits the row modes' register budget (RowWaves): a column of 8 or 16
+// words is held by one thread, one of 32 words by two lanes.
 template <typename W, int LOGR, int KIND, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PipeWaves<LOGR, MODE>::value, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowWaves<MODE>::value, 8)))
 k_pipe(PipeArgsT<W> a, LimbSetT<W> ls) {
   __shared__ W lds[PG::LDS_WORDS];
   constexpr uint32_t R = 1u << LOGR;
+  constexpr uint32_t CB = pipe_col_blocks(LOGR);
   const size_t N = (size_t)1 << (PIPE_LC + LOGR), C = (size_t)1 << PIPE_LC;
   const uint32_t t = threadIdx.x, b = blockIdx.x;
   if (b < a.nr) {
@@ -62,22 +56,45 @@ k_pipe(PipeArgsT<W> a, LimbSetT<W> ls) {
   const bool fwd = b < a.nr + a.nf;
   const uint32_t idx = fwd ? b - a.nr : b - a.nr - a.nf;
   const uint32_t nops = fwd ? a.nops : 1u;
-  const uint32_t cb = idx % PIPE_CB;
-  const uint32_t rest = idx / PIPE_CB;
+  const uint32_t cb = idx % CB;
+  const uint32_t rest = idx / CB;
   const uint32_t op = rest % nops;
   const uint32_t prod = (fwd ? a.f0 : a.i0) + rest / nops;
   const uint32_t limb = prod / a.polys;
-  const size_t off = (size_t)prod * N + (size_t)cb * 256 + t;
-  const W* src = fwd ? (op ? a.B : a.A) + off : a.C + off;
-  W* dst = fwd ? (op ? a.WS : a.C) + off : a.C + off;
   const typename ModOf<W>::type M = ls.mod[limb];
-  W x[R];
+  const W* tw = (fwd ? a.twf : a.twi) + (size_t)limb * N;
+  if constexpr (LOGR == 5) {
+    // lanes l and l + 32 of a wave share a column
+    const uint32_t lane = t & 63, h = lane >> 5;
+    const size_t off = (size_t)prod * N + (size_t)cb * 128 + (t >> 6) * 32 + (lane & 31);
+    const W* src = fwd ? (op ? a.B : a.A) + off : a.C + off;
+    W* dst = fwd ? (op ? a.WS : a.C) + off : a.C + off;
+    W y[16];
+    if (fwd) {
 #pragma unroll
-  for (uint32_t i = 0; i < R; ++i) x[i] = src[i * C];
-  if (fwd) col_fwd<LOGR, KIND>(x, a.twf + (size_t)limb * N, M);
-  else col_inv<LOGR, KIND>(x, a.twi + (size_t)limb * N, M);
+      for (int j = 0; j < 16; ++j) y[j] = src[col32_split_row(j, h) * C];
+      col32_fwd_pair<KIND>(y, tw, h, M);
 #pragma unroll
-  for (uint32_t i = 0; i < R; ++i) dst[i * C] = x[i];
+      for (int j = 0; j < 16; ++j) dst[col32_block_row(j, h) * C] = y[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) y[j] = src[col32_block_row(j, h) * C];
+      col32_inv_pair<KIND>(y, tw, h, M);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) dst[col32_split_row(j, h) * C] = y[j];
+    }
+  } else {
+    const size_t off = (size_t)prod * N + (size_t)cb * 256 + t;
+    const W* src = fwd ? (op ? a.B : a.A) + off : a.C + off;
+    W* dst = fwd ? (op ? a.WS : a.C) + off : a.C + off;
+    W x[R];
+#pragma unroll
+    for (uint32_t i = 0; i < R; ++i) x[i] = src[i * C];
+    if (fwd) col_fwd<LOGR, KIND>(x, tw, M);
+    else col_inv<LOGR, KIND>(x, tw, M);
+#pragma unroll
+    for (uint32_t i = 0; i < R; ++i) dst[i * C] = x[i];
+  }
 }
 
 template <typename W, int LOGR, int MODE>

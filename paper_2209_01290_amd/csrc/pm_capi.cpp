@@ -346,8 +346,8 @@ size_t polymul_workspace(size_t N, size_t limbs, size_t polys) {
 
 // Chunks of the software-pipelined product for a launch group of np
 // products with a column radix of 2^logr, unless pm_tune_set_pipeline chose:
-// 2 when the row pass has at least plan_pipe_rows(logr) rows (2048, 8192 for
-// radix 32, unless tuned), else 0 (the three-pass form). Each chunk's rows
+// 2 when the row pass has at least plan_pipe_rows(logr) rows (2048 unless
+// tuned), else 0 (the three-pass form). Each chunk's rows
 // are one more phase on the critical path, and a row workgroup alone on its
 // CU is bound by latency, so the overlap pays only once the rows fill the CUs
 // several times over. At most PIPE_MAX_CHUNKS chunks and at most np.
@@ -408,17 +408,18 @@ int polymul_common(const W* a, const W* b_, W* c, size_t N, size_t limbs, size_t
       if (G > 1 && p.ebx == 4 && p.logc == 12 && p.logr >= 3 && p.logr <= 5) {
         const uint32_t nops = same ? 1u : 2u;
         const uint32_t R = 1u << p.logr;
-        // a launch holds at most (R + 48) * ceil(np / G) workgroups; keep its
-        // grid under 2^32 threads (a = b: fewer)
-        const size_t cap = (((size_t)1 << 24) - 1) / (R + 48);
+        // a launch holds at most (R + 3 cbs) * ceil(np / G) workgroups (rows,
+        // two forward operands, inverse); keep its grid under 2^32 threads
+        const uint32_t cbs = pipe_col_blocks((int)p.logr);
+        const size_t cap = (((size_t)1 << 24) - 1) / (R + 3 * cbs);
         G = std::max<uint32_t>(G, (uint32_t)((np + cap - 1) / cap));
         auto lo = [&](uint32_t k) { return (uint32_t)(k * np / G); };   // chunk k = products [lo(k), lo(k+1))
         for (uint32_t j = 0; j < G + 2; ++j) {
           PipeArgsT<W> pa{A + base, B + base, c + base, same ? c + base : ws + base, tf, ti, (uint32_t)polys,
                           0, 0, 0, 0, 0, 0, nops};
           if (j >= 1 && j <= G) pa.r0 = lo(j - 1), pa.nr = R * (lo(j) - lo(j - 1));
-          if (j < G) pa.f0 = lo(j), pa.nf = 16u * nops * (lo(j + 1) - lo(j));
-          if (j >= 2) pa.i0 = lo(j - 2), pa.ni = 16u * (lo(j - 1) - lo(j - 2));
+          if (j < G) pa.f0 = lo(j), pa.nf = cbs * nops * (lo(j + 1) - lo(j));
+          if (j >= 2) pa.i0 = lo(j - 2), pa.ni = cbs * (lo(j - 1) - lo(j - 2));
           static const char* const names[2][3] = {{"pipe32_mul_c12", "pipe32_fmul_c12", "pipe32_sqr_c12"},
                                                   {"pipe_mul_c12", "pipe_fmul_c12", "pipe_sqr_c12"}};
           ProfScope ps(s, names[sizeof(W) == 8][mode == ROW_FMUL ? 1 : (mode == ROW_SQR ? 2 : 0)]);

@@ -29,6 +29,12 @@ using LimbSet32 = LimbSetT<uint32_t>;
 
 enum { ROW_FWD = 0, ROW_INV = 1, ROW_MUL = 2, ROW_SQR = 3, ROW_FMUL = 4 };
 
+// Column workgroups (256 threads) per operand of one product in the
+// software-pipelined kernels (rows of 2^12 words, column radix 2^logr): one
+// thread per column, 256 columns each; for logr = 5 two lanes per column,
+// 128 columns each.
+constexpr uint32_t pipe_col_blocks(int logr) { return logr == 5 ? 32u : 16u; }
+
 template <typename W>
 struct RowArgsT {
   const W* A;             // input rows (FWD/INV: in place with C allowed)

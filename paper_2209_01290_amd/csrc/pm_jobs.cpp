@@ -5,7 +5,8 @@
 //
 // Two forms:
 //   * three-pass: each pass is one launch over the work items of all jobs
-//     (three, or up to five with tuned long rows, launches whatever the mix);
+//     (three to six launches whatever the mix: rows up to 2^11, of 2^12 and tuned
+//     long rows go to separate row kernels);
 //   * software-pipelined (batches whose jobs of N >= 2^12 hold at least
 //     JOBS_PIPE_MIN_ROWS rows of 2^12 words): those jobs take rows of 2^12
 //     words, their products are split into G chunks of about equal work, and
@@ -38,9 +39,11 @@ using namespace pm;
 
 namespace {
 
-// maps: three-pass colf, row12, row13, row14, coli; pipelined rows, colf, coli
-constexpr int NGROUP = 8;
-enum { G_COLF = 0, G_ROW12 = 1, G_ROW13 = 2, G_ROW14 = 3, G_COLI = 4, G_PROW = 5, G_PCOLF = 6, G_PCOLI = 7 };
+// maps: three-pass colf, row12, row13, row14, coli; pipelined rows, colf, coli;
+// three-pass rows of up to 2^11 words
+constexpr int NGROUP = 9;
+enum { G_COLF = 0, G_ROW12 = 1, G_ROW13 = 2, G_ROW14 = 3, G_COLI = 4, G_PROW = 5, G_PCOLF = 6, G_PCOLI = 7,
+       G_ROW11 = 8 };
 
 struct Layout {
   std::vector<JobDev> jobs;            // device pointers patched once the base is known
@@ -70,8 +73,8 @@ bool plan_pipeline(Layout* L, const std::vector<uint32_t>& pjobs, uint32_t G) {
   auto per_product = [&](const JobDev& J, uint64_t* rows, uint64_t* colf, uint64_t* coli) {
     const uint64_t R = 1ull << J.logr;
     *rows = R;
-    *colf = R > 1 ? 16ull * J.nops : 0;
-    *coli = R > 1 ? 16 : 0;
+    *colf = R > 1 ? (uint64_t)pipe_col_blocks(J.logr) * J.nops : 0;
+    *coli = R > 1 ? pipe_col_blocks(J.logr) : 0;
   };
   long double W = 0;
   for (uint32_t j : pjobs) {
@@ -217,7 +220,7 @@ int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
     };
     bool ok = true;
     if (pj) {
-      const uint64_t cols = R > 1 ? 16ull * J.count : 0;
+      const uint64_t cols = R > 1 ? (uint64_t)pipe_col_blocks(J.logr) * J.count : 0;
       ok = add(G_PROW, PH_ROW, (uint64_t)J.count * R) && add(G_PCOLF, PH_COLF, cols * J.nops) &&
            add(G_PCOLI, PH_COLI, cols);
     } else {
@@ -225,7 +228,7 @@ int build_layout(const pm_job* jobs, size_t njobs, Layout* L) {
         const uint64_t cbs = 1ull << (J.logc - 8);
         ok = add(G_COLF, PH_COLF, (uint64_t)J.nops * J.count * cbs) && add(G_COLI, PH_COLI, (uint64_t)J.count * cbs);
       }
-      const int g = J.logc <= 12 ? G_ROW12 : (J.logc == 13 ? G_ROW13 : G_ROW14);
+      const int g = J.logc <= 11 ? G_ROW11 : (J.logc == 12 ? G_ROW12 : (J.logc == 13 ? G_ROW13 : G_ROW14));
       const uint64_t rows_per_item = J.logc <= 12 ? (4096u >> J.logc) : 1;   // RowGeom<logc>::ROWS
       const uint64_t tasks = (uint64_t)J.count * R;
       ok = ok && add(g, PH_ROW, (tasks + rows_per_item - 1) / rows_per_item);
@@ -271,9 +274,9 @@ hipError_t launch_all(const Layout& L, char* dev_base, hipStream_t s, bool timed
   const JobDev* jobs = (const JobDev*)dev_base;
   auto map = [&](int g) { return (const uint32_t*)(dev_base + L.off_map[g]); };
   struct Step { int group, phase, maxlogc; const char* name; };
-  static const Step steps[5] = {{G_COLF, PH_COLF, 0, "jobs_col_fwd"}, {G_ROW12, PH_ROW, 12, "jobs_row_mul_c12"},
-                                {G_ROW13, PH_ROW, 13, "jobs_row_mul_c13"}, {G_ROW14, PH_ROW, 14, "jobs_row_mul_c14"},
-                                {G_COLI, PH_COLI, 0, "jobs_col_inv"}};
+  static const Step steps[6] = {{G_COLF, PH_COLF, 0, "jobs_col_fwd"}, {G_ROW11, PH_ROW, 11, "jobs_row_mul_c11"},
+                                {G_ROW12, PH_ROW, 12, "jobs_row_mul_c12"}, {G_ROW13, PH_ROW, 13, "jobs_row_mul_c13"},
+                                {G_ROW14, PH_ROW, 14, "jobs_row_mul_c14"}, {G_COLI, PH_COLI, 0, "jobs_col_inv"}};
   for (const Step& st : steps) {
     const uint32_t n = (uint32_t)L.map[st.group].size();
     if (n == 0) continue;

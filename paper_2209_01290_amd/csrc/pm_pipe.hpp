@@ -11,8 +11,8 @@ namespace pm {
 // limb * polys + poly (indices within the launch group): r0 / f0 / i0 = first
 // product of the row, forward-column and inverse-column chunk; nr / nf / ni =
 // workgroups of each kind (0 when absent): nr = 2^logr per product (one per
-// row), nf = nops * 16 per product (nops operands, 16 blocks of 256
-// columns), ni = 16 per product. nops = 1 when a = b (squaring): the forward
+// row), nf = nops * pipe_col_blocks(logr) per product (nops operands),
+// ni = pipe_col_blocks(logr) per product. nops = 1 when a = b (squaring): the forward
 // column pass transforms a alone into C, and the rows read C for both.
 template <typename W>
 struct PipeArgsT {

@@ -85,7 +85,7 @@ int plan_pipe() { return g_pipe.load(); }
 
 namespace {
 // built-in thresholds, from a sweep of batch sizes on MI355X (2^15..2^17)
-constexpr size_t PIPE_MIN_ROWS_DEFAULT[3] = {2048, 2048, 8192};
+constexpr size_t PIPE_MIN_ROWS_DEFAULT[3] = {2048, 2048, 2048};
 std::atomic<size_t> g_pipe_rows[3] = {{0}, {0}, {0}};
 }  // namespace
 

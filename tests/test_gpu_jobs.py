@@ -167,9 +167,10 @@ def test_jobs_pipelined(L, chunks):
         L.pm_tune_set_jobs_pipeline(-1)
     _check_all(L, keep, want, "pipelined G=%d" % chunks)
     # the jobs of N >= 2^12 ran in pipelined launches (at most G + 2), the
-    # smaller ones in one three-pass row launch before them
+    # smaller ones in one three-pass row launch (rows up to 2^11) before them
     assert 1 <= counts.get("jobs_pipe_mul_c12", 0) <= chunks + 2, counts
-    assert counts.get("jobs_row_mul_c12", 0) == 1 and "jobs_col_fwd" not in counts, counts
+    assert counts.get("jobs_row_mul_c11", 0) == 1 and "jobs_col_fwd" not in counts, counts
+    assert "jobs_row_mul_c12" not in counts, counts
 
 
 def test_plan_replays_pipelined(L):

@@ -65,10 +65,10 @@ def _run(L, fn, a, b, N, qs, dfw, div, chunks, alias=None):
 
 
 def auto_chunks(log2n, products):
-    """The built-in choice: 2 chunks from 2048 rows of 2^12 words (8192 for
-    N = 2^17), else the three-pass form."""
+    """The built-in choice: 2 chunks from 2048 rows of 2^12 words, else the
+    three-pass form."""
     rows = products << (log2n - 12)
-    return 2 if rows >= (8192 if log2n >= 17 else 2048) else 0
+    return 2 if rows >= 2048 else 0
 
 
 # (log2 N, limbs, polys, chunks): chunks of unequal size, chunks that end
@@ -122,25 +122,28 @@ def test_pipelined_aliasing(L, alias, fused):
     _assert_equal(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "c==%s" % alias)
 
 
+@pytest.mark.parametrize("log2n", [16, 17])
 @pytest.mark.parametrize("bits", [62, 61, 34, 33])
-def test_pipelined_other_moduli(L, bits):
-    """Moduli outside the 60-bit window take the general reduction kernels."""
-    N, limbs, polys = 1 << 16, 2, 2
-    L.pm_tune_set(L.OP_POLYMUL, 16, 12)
+def test_pipelined_other_moduli(L, bits, log2n):
+    """Moduli outside the 60-bit window take the general reduction kernels
+    (at N = 2^17 also in the column pass shared by two lanes)."""
+    N, limbs, polys = 1 << log2n, 2, 2
+    L.pm_tune_set(L.OP_POLYMUL, log2n, 12)
     qs = L.pm_ntt_primes(N, limbs, bits)
     fw_o, iv_o = oracle_tables(qs, N)
     _, _, dfw, div = device_tables(qs, N)
-    a, b = operands(N, qs, polys, request=770 + bits)
+    a, b = operands(N, qs, polys, request=770 + bits + log2n)
     for fn in (L.pm_polymul, L.pm_polymul_fused):
         got, prof = _run(L, fn, a, b, N, qs, dfw, div, 2)
         assert any(k.startswith("pipe_") for k in prof), prof
         _assert_equal(got, oracle_polymul(a, b, qs, N, fw_o, iv_o), "%d-bit %s" % (bits, fn.__name__))
 
 
-def test_pipelined_edge_values(L):
+@pytest.mark.parametrize("log2n", [16, 17])
+def test_pipelined_edge_values(L, log2n):
     """Every coefficient q - 1 (the largest products), and zeros."""
-    N, limbs, polys = 1 << 16, 2, 2
-    L.pm_tune_set(L.OP_POLYMUL, 16, 12)
+    N, limbs, polys = 1 << log2n, 2, 2
+    L.pm_tune_set(L.OP_POLYMUL, log2n, 12)
     qs = L.pm_ntt_primes(N, limbs)
     fw_o, iv_o = oracle_tables(qs, N)
     _, _, dfw, div = device_tables(qs, N)
