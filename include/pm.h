@@ -304,9 +304,9 @@ size_t pm_tune_get_small_limit(int op, unsigned log2n);
  * j does the row pass of chunk j-1, the forward column pass of chunk j and
  * the inverse column pass of chunk j-2, so that the memory-bound column work
  * overlaps the VALU-bound rows. chunks = -1 (the default) pipelines a launch
- * group over 2 chunks when its row pass has at least 2048 rows (unless
- * tuned: pm_tune_set_pipeline_rows), i.e. from 256 / 128 / 64 products at
- * N = 2^15 / 2^16 / 2^17:
+ * group over 2 chunks when its row pass has at least 2048 rows (never at
+ * N = 2^17; unless tuned: pm_tune_set_pipeline_rows), i.e. from 256 / 128
+ * products at N = 2^15 / 2^16:
  * each chunk's rows add a phase to the critical path, which pays only for
  * batches that fill the GPU several times over; 0 or 1 never pipelines;
  * G >= 2 uses G chunks (at most 64 and at most the group's products; more
@@ -320,8 +320,8 @@ int pm_tune_get_pipeline(void);
  * The threshold of the default (chunks = -1) pipelining above, per column
  * radix 2^logr (logr = 3, 4, 5: N = 2^15, 2^16, 2^17 with rows of 2^12
  * words): a launch group is pipelined over 2 chunks when its row pass has
- * at least min_rows rows. min_rows = 0 restores the built-in value (2048);
- * SIZE_MAX never pipelines that radix. The autotuner
+ * at least min_rows rows. min_rows = 0 restores the built-in value (2048;
+ * SIZE_MAX for logr = 5); SIZE_MAX never pipelines that radix. The autotuner
  * measures it (tune.py --pipeline) and lib.apply_tune_db installs it.
  * Process-wide, read when a call is made. PM_EINVAL for logr outside 3..5;
  * pm_tune_get_pipeline_rows returns the threshold in effect (0 for an

@@ -346,8 +346,8 @@ size_t polymul_workspace(size_t N, size_t limbs, size_t polys) {
 
 // Chunks of the software-pipelined product for a launch group of np
 // products with a column radix of 2^logr, unless pm_tune_set_pipeline chose:
-// 2 when the row pass has at least plan_pipe_rows(logr) rows (2048 unless
-// tuned), else 0 (the three-pass form). Each chunk's rows
+// 2 when the row pass has at least plan_pipe_rows(logr) rows (2048, never
+// for radix 32, unless tuned), else 0 (the three-pass form). Each chunk's rows
 // are one more phase on the critical path, and a row workgroup alone on its
 // CU is bound by latency, so the overlap pays only once the rows fill the CUs
 // several times over. At most PIPE_MAX_CHUNKS chunks and at most np.

@@ -84,8 +84,9 @@ void plan_pipe_set(int chunks) { g_pipe.store(chunks < 0 ? -1 : chunks); }
 int plan_pipe() { return g_pipe.load(); }
 
 namespace {
-// built-in thresholds, from a sweep of batch sizes on MI355X (2^15..2^17)
-constexpr size_t PIPE_MIN_ROWS_DEFAULT[3] = {2048, 2048, 2048};
+// built-in thresholds, from a sweep of batch sizes on MI355X (2^15..2^17):
+// at 2^17 the three passes are the faster form at every batch size
+constexpr size_t PIPE_MIN_ROWS_DEFAULT[3] = {2048, 2048, SIZE_MAX};
 std::atomic<size_t> g_pipe_rows[3] = {{0}, {0}, {0}};
 }  // namespace
 

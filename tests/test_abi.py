@@ -263,7 +263,7 @@ def test_pipeline_setting():
 
 def test_pipeline_rows_setting():
     """pm_tune_set_pipeline_rows: per column radix 2^3..2^5, 0 restores the
-    built-in threshold (2048), other radices are rejected;
+    built-in threshold (2048; never for radix 32), other radices are rejected;
     the packaged database installs its tuned thresholds."""
     from paper_2209_01290_amd import lib as L
     L.load()
@@ -271,7 +271,7 @@ def test_pipeline_rows_setting():
     try:
         for r in (3, 4, 5):
             L.pm_tune_set_pipeline_rows(r, 0)
-        assert [L.pm_tune_get_pipeline_rows(r) for r in (3, 4, 5)] == [2048, 2048, 2048]
+        assert [L.pm_tune_get_pipeline_rows(r) for r in (3, 4, 5)] == [2048, 2048, (1 << 64) - 1]
         L.pm_tune_set_pipeline_rows(4, 12345)
         assert L.pm_tune_get_pipeline_rows(4) == 12345
         L.pm_tune_set_pipeline_rows(5, (1 << 64) - 1)

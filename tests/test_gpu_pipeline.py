@@ -65,10 +65,10 @@ def _run(L, fn, a, b, N, qs, dfw, div, chunks, alias=None):
 
 
 def auto_chunks(log2n, products):
-    """The built-in choice: 2 chunks from 2048 rows of 2^12 words, else the
-    three-pass form."""
+    """The built-in choice: 2 chunks from 2048 rows of 2^12 words (never at
+    N = 2^17), else the three-pass form."""
     rows = products << (log2n - 12)
-    return 2 if rows >= 2048 else 0
+    return 2 if rows >= 2048 and log2n < 17 else 0
 
 
 # (log2 N, limbs, polys, chunks): chunks of unequal size, chunks that end
