@@ -369,12 +369,18 @@ int pm_polymul_jobs(const pm_job* jobs, size_t njobs, void* workspace, size_t wo
     Stage& st = g_stage[g_stage_next++ % 4];
     if (st.used && hipEventSynchronize(st.done) != hipSuccess) return set_error(PM_EHIP, "staging wait failed");
     if (st.cap < L.table_bytes) {
+      // Freeing pinned memory can wait for the whole device, and pinning
+      // takes time of its own: grow a slot in powers of two from 4 MiB (the
+      // table of 4096 jobs of one product of N = 2^17 is under 3 MiB), so a
+      // slot is reallocated rarely, if ever.
+      size_t cap = (size_t)4 << 20;
+      while (cap < L.table_bytes) cap <<= 1;
       if (st.buf) (void)hipHostFree(st.buf);
       st.buf = nullptr;
       st.cap = 0;
-      if (hipHostMalloc((void**)&st.buf, L.table_bytes, hipHostMallocDefault) != hipSuccess)
+      if (hipHostMalloc((void**)&st.buf, cap, hipHostMallocDefault) != hipSuccess)
         return set_error(PM_ENOMEM, "pinned staging allocation failed");
-      st.cap = L.table_bytes;
+      st.cap = cap;
     }
     if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess)
       return set_error(PM_EHIP, "event creation failed");
