@@ -125,8 +125,8 @@ def mix_ceiling(name: str, N: int, limbs: int, polys: int, rates: dict) -> float
 # The sources the reported kernels are compiled from: the counter summary
 # stays valid while these are unchanged (host-only files do not matter).
 ROW_KERNEL_SOURCES = ("modarith.hpp", "modarith32.hpp", "ntt_device.hpp", "ntt_row.hpp", "pm_internal.hpp",
-                      "row_kernel.inc", "row_12.hip", "row_12r.hip", "pm_kernels.hip", "pipe_kernels.hip",
-                      "pm_pipe.hpp")
+                      "row_kernel.inc", "row_12.hip", "row_fixed.inc", "row_12r.hip", "pm_kernels.hip",
+                      "pipe_kernels.hip", "pm_pipe.hpp")
 
 
 def kernel_source_hash() -> str:

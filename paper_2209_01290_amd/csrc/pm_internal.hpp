@@ -72,10 +72,12 @@ hipError_t launch_row(int logc, int kind, int mode, const RowArgsT<uint32_t>& a,
 PM_DECL_ROW(1) PM_DECL_ROW(2) PM_DECL_ROW(3) PM_DECL_ROW(4) PM_DECL_ROW(5) PM_DECL_ROW(6) PM_DECL_ROW(7)
 PM_DECL_ROW(8) PM_DECL_ROW(9) PM_DECL_ROW(10) PM_DECL_ROW(11) PM_DECL_ROW(12) PM_DECL_ROW(13) PM_DECL_ROW(14)
 #undef PM_DECL_ROW
-// The product rows (ROW_MUL, ROW_FMUL) of 2^12 words, 64-bit words, moduli
-// of 34..61 bits, with the split's radix fixed at compile time
-// (row_12r.hip); false, launching nothing, for other modes, kinds or shapes.
+// The product rows (ROW_MUL, ROW_FMUL) of 2^12 words with the split's radix
+// fixed at compile time (row_fixed.inc): 64-bit words with moduli of 34..61
+// bits (row_12r.hip), 32-bit words (row_12r32.hip); false, launching
+// nothing, for other modes, kinds or shapes.
 bool launch_row12_fixed(int kind, int mode, const RowArgs& a, hipStream_t s);
+bool launch_row12_fixed(int kind, int mode, const RowArgsT<uint32_t>& a, hipStream_t s);
 hipError_t launch_col(int logr, int kind, bool inv, const ColArgs& a, hipStream_t s);
 hipError_t launch_col(int logr, int kind, bool inv, const ColArgsT<uint32_t>& a, hipStream_t s);
 
